@@ -1,0 +1,200 @@
+/*
+ * pct.h -- C ABI of the MI355X (gfx950) proton-CT reconstruction hot path.
+ *
+ * The problem (Karbasi et al., "A Highly Accelerated Parallel Multi-GPU based
+ * Reconstruction Algorithm for Generating Accurate Relative Stopping Powers",
+ * Section I): protons are tracked on entry to and exit from the object; each
+ * proton's most likely path (MLP) through the voxel grid gives one sparse row
+ * a_i of A (the chord length of the path in every voxel), b_i is its measured
+ * water-equivalent path length (WEPL) and x the relative stopping power (RSP)
+ * of every voxel.  A x = b is solved iteratively (Section III) with the
+ * block-iterative DROP method, one block being the protons processed in
+ * parallel (Section IV-B).
+ *
+ * The paper cites the MLP and DROP formulas without printing them.  This
+ * library implements:
+ *   MLP   -- the maximum-likelihood path of Schulte et al. (Med. Phys. 35,
+ *            2008) between two fixed tracker planes u_in < u_out of the beam
+ *            frame, sampled every `step` mm; the path is the polyline through
+ *            those vertices;
+ *   row   -- Siddon's ray/grid intersection on every polyline segment, voxel
+ *            of a piece from its midpoint, half-open voxels; a_ij is the sum
+ *            of the chords of the path inside voxel j;
+ *   DROP  -- for every block t of B consecutive protons (input order),
+ *            rho_i = lambda (b_i - a_i.x) / ||a_i||^2 and
+ *            x_j += (sum_i rho_i a_ij) / s_j, s_j = number of block rows that
+ *            touch voxel j; rows with ||a_i|| = 0 are skipped.
+ *
+ * Frames and units.  Lab frame (x, y, z) in mm.  Voxel (ix, iy, iz) covers
+ * [origin + i*pitch, origin + (i+1)*pitch) on each axis and has flat index
+ * j = ix + nx*(iy + ny*iz).  At gantry angle phi the beam frame is
+ * e_u = (cos phi, sin phi, 0), e_t = (-sin phi, cos phi, 0), e_v = (0, 0, 1);
+ * a tracker measurement (t, v, th, ph) is a lateral position (mm) and the
+ * slopes dt/du, dv/du.
+ *
+ * Memory.  Every data pointer passed to a compute call (proton arrays, b, x,
+ * y, r, g, trace outputs, the workspace) is DEVICE memory owned by the
+ * caller.  The library allocates no device memory: all scratch lives in a
+ * caller-provided workspace of pct_workspace_size() bytes, which must first
+ * be initialised by pct_plan_upload().  Calls are asynchronous on `stream`
+ * (a hipStream_t; NULL is the null stream); results are valid once the caller
+ * synchronises that stream.
+ *
+ * Errors.  Every call returns PCT_OK (0) or a negative status.  All argument
+ * checks run on the host before anything is enqueued, so a call that returns
+ * an argument error has launched nothing.  Conditions only the device can see
+ * (a row longer than the caller's trace buffer, a re-entry pattern outside the
+ * kernel's window, non-finite inputs) are recorded in a status word inside
+ * the workspace and read back with pct_device_status().
+ */
+#ifndef PCT_H
+#define PCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PCT_OK 0
+#define PCT_ERR_INVALID_ARG (-1)   /* a pointer, size, geometry or option is invalid     */
+#define PCT_ERR_WORKSPACE (-2)     /* workspace missing, too small or not uploaded        */
+#define PCT_ERR_ROW_OVERFLOW (-3)  /* (device) a traced row exceeded max_nnz              */
+#define PCT_ERR_NONFINITE (-4)     /* (device) a proton record or b_i was NaN/Inf        */
+#define PCT_ERR_REENTRY (-5)       /* (device) a voxel re-entry outside the kernel window */
+#define PCT_ERR_HIP (-6)           /* a HIP runtime call failed (see pct_last_hip_error)  */
+#define PCT_ERR_UNSUPPORTED (-7)   /* valid request this build does not implement         */
+
+/* device status bits returned by pct_device_status() */
+#define PCT_DEV_ROW_OVERFLOW 0x1u
+#define PCT_DEV_NONFINITE 0x2u
+#define PCT_DEV_REENTRY 0x4u
+
+/* ---- value and chord types --------------------------------------------- */
+typedef enum {
+    PCT_F32 = 0, /* float  */
+    PCT_F64 = 1  /* double */
+} pct_dtype;
+
+/* Precision of the chord lengths a_ij used by the solver.  Chords are always
+ * computed in FP64; F32/F16/BF16 round each merged chord to FP32 and then to
+ * the narrower format (round to nearest, ties to even) before any use. */
+typedef enum {
+    PCT_CHORD_F64 = 0,
+    PCT_CHORD_F32 = 1,
+    PCT_CHORD_F16 = 2,
+    PCT_CHORD_BF16 = 3
+} pct_chord;
+
+/* ---- geometry and model ------------------------------------------------ */
+typedef struct {
+    int32_t nx, ny, nz; /* voxels per axis, each > 0, nx*ny*nz < 2^31              */
+    double pitch[3];    /* voxel size per axis (mm), > 0                           */
+    double origin[3];   /* lab coordinates of the grid's minimum corner (mm)       */
+} pct_grid;
+
+typedef struct {
+    double u_in, u_out; /* tracker planes along the beam axis (mm), u_in < u_out   */
+    double step;        /* MLP vertex spacing in depth (mm), > 0                   */
+    double poly[6];     /* 1/(beta^2 p^2) = sum_k poly[k] s^k [MeV^-2], s = depth
+                           from u_in in cm                                          */
+    double E0;          /* Highland constant (MeV), > 0                            */
+    double X0;          /* radiation length (cm), > 0                              */
+    int32_t log_term;   /* 1: scattering matrices carry (1 + 0.038 ln(L/X0))^2     */
+} pct_mlp;
+
+/* Structure-of-arrays proton records, n entries each, float32 device arrays. */
+typedef struct {
+    const float *t_in, *v_in;   /* entry lateral positions (mm) at u_in          */
+    const float *th_in, *ph_in; /* entry slopes dt/du, dv/du                      */
+    const float *t_out, *v_out; /* exit lateral positions (mm) at u_out          */
+    const float *th_out, *ph_out;
+    const float *gantry;        /* gantry angle phi (rad)                         */
+    int64_t n;                  /* number of protons, >= 0                        */
+} pct_protons;
+
+/* ---- plan --------------------------------------------------------------- */
+/* Host object holding the grid, the MLP model and its FP64 coefficient table
+ * (one row per vertex: t_k = c0t t_in + c0th th_in + c2t t_out + c2th th_out).
+ * Immutable after pct_plan_upload(); calls on different streams may share it
+ * as long as each uses its own workspace. */
+typedef struct pct_plan pct_plan;
+
+int pct_plan_create(const pct_grid *grid, const pct_mlp *mlp, pct_plan **out);
+void pct_plan_destroy(pct_plan *plan);
+
+/* Number of polyline segments K (vertices 0..K). */
+int pct_plan_segments(const pct_plan *plan, int32_t *K);
+
+/* Copies the host coefficient table, (K+1) rows of (c0t, c0th, c2t, c2th), into
+ * host memory `tab` of (K+1)*4 doubles. */
+int pct_plan_table(const pct_plan *plan, double *tab, int64_t tab_len);
+
+/* DROP options. */
+typedef struct {
+    int64_t block;       /* protons per block B, > 0                                */
+    double lambda;       /* relaxation, finite, > 0                                 */
+    int32_t n_iter;      /* sweeps over all blocks, >= 0                            */
+    int32_t dtype;       /* pct_dtype of x (accumulators use the same type)         */
+    int32_t chord;       /* pct_chord                                               */
+    uint32_t flags;      /* PCT_DROP_* bits                                         */
+    int64_t block_begin; /* first block of every sweep (>= 0)                       */
+    int64_t block_end;   /* one past the last block; < 0 means ceil(n/B)            */
+} pct_drop_opts;
+
+#define PCT_DROP_CHECK_FINITE 0x1u /* scan records and b for NaN/Inf (device status) */
+#define PCT_DROP_NO_GRAPH 0x2u     /* launch per block on the stream, no HIP graph   */
+
+/* Workspace bytes for problems of this plan (n protons, x of type dtype). */
+int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes);
+
+/* Writes the coefficient table into the workspace and clears its counters and
+ * status word.  Must precede every compute call that uses this workspace. */
+int pct_plan_upload(pct_plan *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* Reads (and with reset != 0 clears) the device status word of the workspace;
+ * synchronises `stream`.  *bits receives PCT_DEV_* flags. */
+int pct_device_status(const pct_plan *plan, void *ws, size_t ws_bytes, int reset, uint32_t *bits, void *stream);
+
+/* ---- entry points of the hot path -------------------------------------- */
+
+/* Row tracing (MLP + voxel walk).  For protons first..first+count-1, writes the
+ * ordered emission list of each path -- (voxel, chord) pieces in path order,
+ * consecutive pieces in the same voxel merged -- to vox/chord rows of stride
+ * max_nnz, and its full length to nnz.  Pieces beyond max_nnz are dropped and
+ * PCT_DEV_ROW_OVERFLOW is raised.  vox: int32[count*max_nnz], chord:
+ * double[count*max_nnz], nnz: int32[count]. */
+int pct_mlp_trace(const pct_plan *plan, const pct_protons *p, int64_t first, int64_t count, int32_t max_nnz,
+                  int32_t *vox, double *chord, int32_t *nnz, void *ws, size_t ws_bytes, void *stream);
+
+/* Forward projection y = A x (and ||a_i||^2 if nrm2 != NULL).  x: dtype[nvox];
+ * y, nrm2: dtype[n]. */
+int pct_forward(const pct_plan *plan, const pct_protons *p, const void *x, int32_t dtype, void *y, void *nrm2,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* Back projection g += A^T r.  r: dtype[n]; g: dtype[nvox], accumulated. */
+int pct_backproject(const pct_plan *plan, const pct_protons *p, const void *r, int32_t dtype, void *g, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Block-iterative DROP: opts->n_iter sweeps over blocks [block_begin,
+ * block_end) updating x in place.  b: float[n]; x: dtype[nvox]. */
+int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b, void *x,
+                     const pct_drop_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/* Smoothed total variation (differentiation form): TV(x) = sum_v sqrt(dx^2 +
+ * dy^2 + dz^2 + eps^2) with forward differences, zero at the last index of
+ * every axis.  Writes the value to value_dev (device double[1]) and, if
+ * grad != NULL, its gradient (float[nvox]).  x: float[nvox]. */
+int pct_tv(const pct_plan *plan, const float *x, double eps, double *value_dev, float *grad, void *ws,
+           size_t ws_bytes, void *stream);
+
+/* ---- diagnostics --------------------------------------------------------- */
+const char *pct_status_string(int status);
+int pct_last_hip_error(void); /* hipError_t of the most recent PCT_ERR_HIP on this thread */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCT_H */

@@ -1,0 +1,221 @@
+"""PyTorch-facing binding of the C ABI, one function per entry point.
+
+Tensors supply device memory; the current torch stream is the stream every
+call is enqueued on.  Nothing here computes: each function checks tensor
+shapes/dtypes/devices, marshals pointers and calls libpct.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import FIELDS, PCT_F32, PCT_F64, check, lib
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return PCT_F32
+    if t.dtype == torch.float64:
+        return PCT_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev(t: torch.Tensor, what: str, dtype=None, numel: Optional[int] = None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A pct_plan plus its device workspace (uploaded once)."""
+
+    def __init__(self, grid, mlp, device="cuda:0", n_hint: int = 0):
+        self.grid = grid
+        self.mlp = mlp
+        self.device = torch.device(device)
+        self.nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
+        h = C.c_void_p()
+        check(lib().pct_plan_create(C.byref(_lib.make_grid(grid)), C.byref(_lib.make_mlp(mlp)), C.byref(h)),
+              "pct_plan_create")
+        self.handle = h
+        k = C.c_int32()
+        check(lib().pct_plan_segments(h, C.byref(k)), "pct_plan_segments")
+        self.K = k.value
+        nbytes = C.c_size_t()
+        check(lib().pct_workspace_size(h, int(n_hint), PCT_F64, C.byref(nbytes)), "pct_workspace_size")
+        self.ws_bytes = nbytes.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = C.c_void_p(self.ws.data_ptr() + off)
+        check(lib().pct_plan_upload(h, self.ws_ptr, self.ws_bytes, _stream(self.device)), "pct_plan_upload")
+
+    def table(self):
+        import numpy as np
+        tab = np.zeros((self.K + 1) * 4)
+        check(lib().pct_plan_table(self.handle, tab.ctypes.data_as(C.POINTER(C.c_double)), tab.size),
+              "pct_plan_table")
+        return tab.reshape(self.K + 1, 4)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pct_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Protons:
+    """Device-resident SoA proton records (float32)."""
+
+    def __init__(self, arrays: dict, device="cuda:0"):
+        self.t = {}
+        n = None
+        for k in FIELDS:
+            a = arrays[k]
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(a)
+            t = t.to(device=device, dtype=torch.float32).contiguous()
+            if n is None:
+                n = t.numel()
+            elif t.numel() != n:
+                raise ValueError("proton arrays differ in length")
+            self.t[k] = t
+        self.n = int(n)
+        self.s = _lib.make_protons({k: self.t[k].data_ptr() for k in FIELDS}, self.n)
+
+    def slice(self, lo: int, hi: int) -> "Protons":
+        return Protons({k: v[lo:hi] for k, v in self.t.items()}, device=self.t["t_in"].device)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def pct_mlp_trace(plan: Plan, p: Protons, first: int = 0, count: Optional[int] = None, max_nnz: int = 512):
+    count = p.n - first if count is None else int(count)
+    dev = plan.device
+    vox = torch.full((count, max_nnz), -1, dtype=torch.int32, device=dev)
+    chord = torch.zeros((count, max_nnz), dtype=torch.float64, device=dev)
+    nnz = torch.zeros(count, dtype=torch.int32, device=dev)
+    st = lib().pct_mlp_trace(plan.handle, C.byref(p.s), int(first), count, int(max_nnz), C.c_void_p(vox.data_ptr()),
+                             C.c_void_p(chord.data_ptr()), C.c_void_p(nnz.data_ptr()), plan.ws_ptr, plan.ws_bytes,
+                             _stream(dev))
+    check(st, "pct_mlp_trace")
+    return vox, chord, nnz
+
+
+def pct_forward(plan: Plan, p: Protons, x: torch.Tensor, with_norm: bool = False, y=None, nrm2=None):
+    code = _dtype_code(x)
+    xp = _dev(x, "x", numel=plan.nvox)
+    y = torch.empty(p.n, dtype=x.dtype, device=x.device) if y is None else y
+    yp = _dev(y, "y", dtype=x.dtype, numel=p.n)
+    n2p = None
+    if with_norm:
+        nrm2 = torch.empty(p.n, dtype=x.dtype, device=x.device) if nrm2 is None else nrm2
+        n2p = _dev(nrm2, "nrm2", dtype=x.dtype, numel=p.n)
+    st = lib().pct_forward(plan.handle, C.byref(p.s), xp, code, yp, n2p, plan.ws_ptr, plan.ws_bytes,
+                           _stream(x.device))
+    check(st, "pct_forward")
+    return (y, nrm2) if with_norm else y
+
+
+def pct_backproject(plan: Plan, p: Protons, r: torch.Tensor, g: Optional[torch.Tensor] = None):
+    code = _dtype_code(r)
+    rp = _dev(r, "r", numel=p.n)
+    g = torch.zeros(plan.nvox, dtype=r.dtype, device=r.device) if g is None else g
+    gp = _dev(g, "g", dtype=r.dtype, numel=plan.nvox)
+    st = lib().pct_backproject(plan.handle, C.byref(p.s), rp, code, gp, plan.ws_ptr, plan.ws_bytes,
+                               _stream(r.device))
+    check(st, "pct_backproject")
+    return g
+
+
+def pct_drop_iterate(plan: Plan, p: Protons, b: torch.Tensor, x: torch.Tensor, block: int, lam: float,
+                     n_iter: int, chord: str = "f64", flags: int = 0, block_begin: int = 0, block_end: int = -1):
+    code = _dtype_code(x)
+    bp = _dev(b, "b", dtype=torch.float32, numel=p.n)
+    xp = _dev(x, "x", numel=plan.nvox)
+    o = _lib.make_opts(block, lam, n_iter, code, chord, flags, block_begin, block_end)
+    st = lib().pct_drop_iterate(plan.handle, C.byref(p.s), bp, xp, C.byref(o), plan.ws_ptr, plan.ws_bytes,
+                                _stream(x.device))
+    check(st, "pct_drop_iterate")
+    return x
+
+
+def pct_tv(plan: Plan, x: torch.Tensor, eps: float, with_grad: bool = True):
+    xp = _dev(x, "x", dtype=torch.float32, numel=plan.nvox)
+    val = torch.zeros(1, dtype=torch.float64, device=x.device)
+    grad = torch.empty_like(x) if with_grad else None
+    st = lib().pct_tv(plan.handle, xp, float(eps), C.c_void_p(val.data_ptr()),
+                      C.c_void_p(grad.data_ptr()) if with_grad else None, plan.ws_ptr, plan.ws_bytes,
+                      _stream(x.device))
+    check(st, "pct_tv")
+    return val, grad
+
+
+def pct_device_status(plan: Plan, reset: bool = True) -> int:
+    bits = C.c_uint32()
+    st = lib().pct_device_status(plan.handle, plan.ws_ptr, plan.ws_bytes, int(reset), C.byref(bits),
+                                 _stream(plan.device))
+    check(st, "pct_device_status")
+    return bits.value
+
+
+# ---------------------------------------------------------------------------
+# differentiation form
+# ---------------------------------------------------------------------------
+class ProjectFn(torch.autograd.Function):
+    """y = A x with the hand-written adjoint: backward is A^T grad_y, the MLP
+    rows being recomputed by the back-projection kernel (nothing is saved but
+    the plan and the proton records)."""
+
+    @staticmethod
+    def forward(ctx, x, plan, protons):
+        ctx.plan = plan
+        ctx.protons = protons
+        return pct_forward(plan, protons, x.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        g = pct_backproject(ctx.plan, ctx.protons, grad_y.contiguous())
+        return g, None, None
+
+
+class TVFn(torch.autograd.Function):
+    """Smoothed total variation with its gradient from the same kernel."""
+
+    @staticmethod
+    def forward(ctx, x, plan, eps):
+        val, grad = pct_tv(plan, x.contiguous(), eps, with_grad=True)
+        ctx.save_for_backward(grad)
+        return val[0].to(x.dtype)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return gout * grad, None, None
+
+
+class DropSolver:
+    """Block-iterative DROP over device-resident protons and WEPL data."""
+
+    def __init__(self, plan: Plan, protons: Protons, b: torch.Tensor):
+        self.plan, self.p, self.b = plan, protons, b
+
+    def run(self, x: torch.Tensor, block: int, lam: float, n_iter: int, chord: str = "f64", **kw):
+        return pct_drop_iterate(self.plan, self.p, self.b, x, block, lam, n_iter, chord=chord, **kw)

@@ -1,0 +1,380 @@
+// Host side of the C ABI: plan construction (MLP coefficient table in FP64),
+// argument validation and dispatch to the HIP launchers.  Every check runs
+// before anything is enqueued on the device.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "pct_internal.h"
+
+namespace pct {
+
+static thread_local int g_last_hip_error = 0;
+
+static int hip_status(int err)
+{
+    if (err == 0) return PCT_OK;
+    g_last_hip_error = err;
+    return PCT_ERR_HIP;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+Layout layout_for(int64_t nvox, int K, int dtype)
+{
+    // Offsets do not depend on the value type: the accumulator always has room
+    // for FP64 values, so one workspace serves both value types.
+    (void)dtype;
+    Layout L{};
+    const size_t vsize = 8;
+    size_t off = 0;
+    L.hdr = off;
+    off += 256;
+    L.table = off;
+    off = align256(off + size_t(K + 1) * kRowDoubles * sizeof(double));
+    L.acc = off;
+    off = align256(off + size_t(nvox) * vsize);
+    L.cnt = off;
+    off = align256(off + size_t(nvox) * sizeof(int32_t));
+    L.touched = off;
+    off = align256(off + size_t(nvox) * sizeof(int32_t));
+    L.partial = off;
+    off = align256(off + size_t(kMaxPartials) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+GridDev grid_dev(const pct_grid &g)
+{
+    GridDev d{};
+    const int32_t n[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = n[a];
+        d.pitch[a] = g.pitch[a];
+        d.lo[a] = g.origin[a];
+        d.hi[a] = g.origin[a] + n[a] * g.pitch[a];
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// MLP coefficient table
+//
+// Scattering matrix of the path from depth lo to depth `end` (cm), seen at
+// `end`:  S = E0^2 l(end - lo) / X0 * [[J2, J1], [J1, J0]],
+//         J_m = integral over [lo, end] of (end - s)^m P(s) ds,
+// P the 1/(beta^2 p^2) polynomial and l(L) = (1 + 0.038 ln(L/X0))^2 (optional).
+// J_m is evaluated with 4-point Gauss-Legendre quadrature, exact for the
+// degree <= 7 integrand.
+//
+// The most likely position at depth d given the entry state y0 = (t, th) and
+// the exit state y2 is the Gaussian posterior mean with prior R0 y0, prior
+// covariance S1 = S(0 -> d) and observation y2 = R1 y1 + N(0, S2),
+// S2 = S(d -> D):  y1 = (I - G R1) R0 y0 + G y2,  G = S1 R1^T (R1 S1 R1^T + S2)^-1.
+// This is algebraically the same as (S1^-1 + R1^T S2^-1 R1)^-1 (S1^-1 R0 y0 +
+// R1^T S2^-1 y2) (Schulte et al. 2008) but needs no inverse of the nearly
+// singular S1 close to the entry plane.
+// ---------------------------------------------------------------------------
+static double poly_at(const pct_mlp &m, double s)
+{
+    double v = 0.0;
+    for (int k = 5; k >= 0; --k) v = v * s + m.poly[k];
+    return v;
+}
+
+static void scatter_matrix(const pct_mlp &m, double lo, double end, double S[4])
+{
+    static const double r1 = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    static const double r2 = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(6.0 / 5.0));
+    static const double w1 = (18.0 + std::sqrt(30.0)) / 36.0;
+    static const double w2 = (18.0 - std::sqrt(30.0)) / 36.0;
+    const double xs[4] = {-r2, -r1, r1, r2};
+    const double ws[4] = {w2, w1, w1, w2};
+    double h = 0.5 * (end - lo), c = 0.5 * (end + lo);
+    double J0 = 0, J1 = 0, J2 = 0;
+    for (int i = 0; i < 4; ++i) {
+        double s = c + h * xs[i];
+        double w = ws[i] * h * poly_at(m, s);
+        double e = end - s;
+        J0 += w;
+        J1 += w * e;
+        J2 += w * e * e;
+    }
+    double f = m.E0 * m.E0 / m.X0;
+    if (m.log_term) {
+        double l = 1.0 + 0.038 * std::log((end - lo) / m.X0);
+        f *= l * l;
+    }
+    S[0] = f * J2;
+    S[1] = f * J1;
+    S[2] = f * J1;
+    S[3] = f * J0;
+}
+
+static bool build_table(pct_plan &pl)
+{
+    const pct_mlp &m = pl.mlp;
+    const double D = m.u_out - m.u_in;
+    const int K = pl.K;
+    pl.table.assign(size_t(K + 1) * kRowDoubles, 0.0);
+    const double Dcm = D / 10.0;
+    for (int k = 0; k <= K; ++k) {
+        double *r = &pl.table[size_t(k) * kRowDoubles];
+        double dk = k * m.step;
+        if (!(dk < D)) dk = D;
+        r[4] = m.u_in + dk;
+        if (k == 0) { r[0] = 1.0; continue; }
+        if (k == K) { r[2] = 1.0; continue; }
+        double d = dk / 10.0;
+        double S1[4], S2[4];
+        scatter_matrix(m, 0.0, d, S1);
+        scatter_matrix(m, d, Dcm, S2);
+        // both scattering matrices must be covariances (positive definite)
+        for (const double *S : {S1, S2})
+            if (!(S[0] > 0.0) || !(S[3] > 0.0) || !(S[0] * S[3] - S[1] * S[2] > 0.0)) return false;
+        const double e = Dcm - d;  // R1 = [[1, e], [0, 1]], R0 = [[1, d], [0, 1]]
+        // T = R1 S1 R1^T + S2
+        double a = S1[0] + 2.0 * e * S1[1] + e * e * S1[3] + S2[0];
+        double b = S1[1] + e * S1[3] + S2[1];
+        double dd = S1[3] + S2[3];
+        double det = a * dd - b * b;
+        double Ti[4] = {dd / det, -b / det, -b / det, a / det};
+        // S1 R1^T = [[S1_00 + e S1_01, S1_01], [S1_10 + e S1_11, S1_11]]
+        double U[4] = {S1[0] + e * S1[1], S1[1], S1[2] + e * S1[3], S1[3]};
+        double G[4] = {U[0] * Ti[0] + U[1] * Ti[2], U[0] * Ti[1] + U[1] * Ti[3],
+                       U[2] * Ti[0] + U[3] * Ti[2], U[2] * Ti[1] + U[3] * Ti[3]};
+        // (I - G R1) R0, first row: [1 - G00, -(G00 e) - G01 + 0] * R0
+        double q0 = 1.0 - G[0];
+        double q1 = -G[0] * e - G[1];
+        double c0t = q0;
+        double c0th = q0 * d + q1;
+        r[0] = c0t;
+        r[1] = c0th * 10.0;
+        r[2] = G[0];
+        r[3] = G[1] * 10.0;
+    }
+    for (double v : pl.table)
+        if (!std::isfinite(v)) return false;
+    return true;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+static int check_grid_mlp(const pct_grid *g, const pct_mlp *m)
+{
+    if (!g || !m) return PCT_ERR_INVALID_ARG;
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return PCT_ERR_INVALID_ARG;
+    if (int64_t(g->nx) * g->ny * g->nz >= (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (!finite_pos(g->pitch[a]) || !std::isfinite(g->origin[a])) return PCT_ERR_INVALID_ARG;
+    if (!std::isfinite(m->u_in) || !std::isfinite(m->u_out) || !(m->u_in < m->u_out)) return PCT_ERR_INVALID_ARG;
+    if (!finite_pos(m->step) || !finite_pos(m->E0) || !finite_pos(m->X0)) return PCT_ERR_INVALID_ARG;
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(m->poly[k])) return PCT_ERR_INVALID_ARG;
+    if (m->log_term != 0 && m->log_term != 1) return PCT_ERR_INVALID_ARG;
+    double K = std::ceil((m->u_out - m->u_in) / m->step);
+    if (!(K >= 1.0) || K > kMaxSegments) return PCT_ERR_INVALID_ARG;
+    return PCT_OK;
+}
+
+static int check_protons(const pct_protons *p)
+{
+    if (!p || p->n < 0) return PCT_ERR_INVALID_ARG;
+    if (p->n > (int64_t(1) << 40)) return PCT_ERR_INVALID_ARG;
+    if (p->n == 0) return PCT_OK;
+    const float *ptrs[9] = {p->t_in, p->v_in, p->th_in, p->ph_in, p->t_out, p->v_out, p->th_out, p->ph_out,
+                            p->gantry};
+    for (const float *q : ptrs)
+        if (!q) return PCT_ERR_INVALID_ARG;
+    return PCT_OK;
+}
+
+static ProtonsDev protons_dev(const pct_protons *p)
+{
+    return ProtonsDev{p->t_in, p->v_in, p->th_in, p->ph_in, p->t_out, p->v_out, p->th_out, p->ph_out, p->gantry};
+}
+
+static int check_ws(const pct_plan *pl, void *ws, size_t ws_bytes, int dtype)
+{
+    if (!ws) return PCT_ERR_WORKSPACE;
+    Layout L = layout_for(pl->nvox, pl->K, dtype);
+    if (ws_bytes < L.total) return PCT_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return PCT_ERR_WORKSPACE;
+    for (int i = 0; i < pl->n_uploaded; ++i)
+        if (pl->uploaded[i] == ws) return PCT_OK;
+    return PCT_ERR_WORKSPACE;
+}
+
+static bool valid_dtype(int32_t d) { return d == PCT_F32 || d == PCT_F64; }
+
+}  // namespace pct
+
+using namespace pct;
+
+extern "C" {
+
+int pct_plan_create(const pct_grid *grid, const pct_mlp *mlp, pct_plan **out)
+{
+    if (!out) return PCT_ERR_INVALID_ARG;
+    *out = nullptr;
+    int st = check_grid_mlp(grid, mlp);
+    if (st) return st;
+    pct_plan *pl = new (std::nothrow) pct_plan();
+    if (!pl) return PCT_ERR_INVALID_ARG;
+    pl->grid = *grid;
+    pl->mlp = *mlp;
+    pl->K = int(std::ceil((mlp->u_out - mlp->u_in) / mlp->step));
+    if (pl->K < 1) pl->K = 1;
+    pl->nvox = int64_t(grid->nx) * grid->ny * grid->nz;
+    pl->n_uploaded = 0;
+    if (!build_table(*pl)) {
+        delete pl;
+        return PCT_ERR_INVALID_ARG;
+    }
+    *out = pl;
+    return PCT_OK;
+}
+
+void pct_plan_destroy(pct_plan *plan) { delete plan; }
+
+int pct_plan_segments(const pct_plan *plan, int32_t *K)
+{
+    if (!plan || !K) return PCT_ERR_INVALID_ARG;
+    *K = plan->K;
+    return PCT_OK;
+}
+
+int pct_plan_table(const pct_plan *plan, double *tab, int64_t tab_len)
+{
+    if (!plan || !tab || tab_len < int64_t(plan->K + 1) * 4) return PCT_ERR_INVALID_ARG;
+    for (int k = 0; k <= plan->K; ++k)
+        for (int c = 0; c < 4; ++c) tab[k * 4 + c] = plan->table[size_t(k) * kRowDoubles + c];
+    return PCT_OK;
+}
+
+int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes)
+{
+    if (!plan || !bytes || n < 0 || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
+    *bytes = layout_for(plan->nvox, plan->K, dtype).total;
+    return PCT_OK;
+}
+
+int pct_plan_upload(pct_plan *plan, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan) return PCT_ERR_INVALID_ARG;
+    if (!ws) return PCT_ERR_WORKSPACE;
+    if (ws_bytes < layout_for(plan->nvox, plan->K, PCT_F32).total) return PCT_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return PCT_ERR_WORKSPACE;
+    int st = hip_status(upload_table(*plan, ws, stream));
+    if (st) return st;
+    bool known = false;
+    for (int i = 0; i < plan->n_uploaded; ++i) known |= plan->uploaded[i] == ws;
+    if (!known) {
+        if (plan->n_uploaded == kMaxUploads) {
+            for (int i = 1; i < kMaxUploads; ++i) plan->uploaded[i - 1] = plan->uploaded[i];
+            plan->n_uploaded--;
+        }
+        plan->uploaded[plan->n_uploaded++] = ws;
+    }
+    return PCT_OK;
+}
+
+int pct_device_status(const pct_plan *plan, void *ws, size_t ws_bytes, int reset, uint32_t *bits, void *stream)
+{
+    if (!plan || !bits) return PCT_ERR_INVALID_ARG;
+    int st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    return hip_status(read_status(*plan, ws, reset, bits, stream));
+}
+
+int pct_mlp_trace(const pct_plan *plan, const pct_protons *p, int64_t first, int64_t count, int32_t max_nnz,
+                  int32_t *vox, double *chord, int32_t *nnz, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (first < 0 || count < 0 || first + count > p->n || max_nnz <= 0) return PCT_ERR_INVALID_ARG;
+    if (count > 0 && (!vox || !chord || !nnz)) return PCT_ERR_INVALID_ARG;
+    if (count * int64_t(max_nnz) >= (int64_t(1) << 40)) return PCT_ERR_INVALID_ARG;
+    st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    if (count == 0) return PCT_OK;
+    return hip_status(launch_trace(*plan, protons_dev(p), first, count, max_nnz, vox, chord, nnz, ws, stream));
+}
+
+int pct_forward(const pct_plan *plan, const pct_protons *p, const void *x, int32_t dtype, void *y, void *nrm2,
+                void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (p->n > 0 && (!x || !y)) return PCT_ERR_INVALID_ARG;
+    st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    if (p->n == 0) return PCT_OK;
+    return hip_status(launch_forward(*plan, protons_dev(p), p->n, x, dtype, y, nrm2, ws, stream));
+}
+
+int pct_backproject(const pct_plan *plan, const pct_protons *p, const void *r, int32_t dtype, void *g, void *ws,
+                    size_t ws_bytes, void *stream)
+{
+    if (!plan || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (p->n > 0 && (!r || !g)) return PCT_ERR_INVALID_ARG;
+    st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    if (p->n == 0) return PCT_OK;
+    return hip_status(launch_backproject(*plan, protons_dev(p), p->n, r, dtype, g, ws, stream));
+}
+
+int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b, void *x,
+                     const pct_drop_opts *o, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !o) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (!x) return PCT_ERR_INVALID_ARG;
+    if (p->n > 0 && !b) return PCT_ERR_INVALID_ARG;
+    if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
+    if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
+    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH)) return PCT_ERR_INVALID_ARG;
+    if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
+    int64_t T = p->n > 0 ? (p->n + o->block - 1) / o->block : 0;
+    int64_t end = o->block_end < 0 ? T : o->block_end;
+    if (o->block_begin < 0 || end > T || o->block_begin > end) return PCT_ERR_INVALID_ARG;
+    st = check_ws(plan, ws, ws_bytes, o->dtype);
+    if (st) return st;
+    if (o->n_iter == 0 || o->block_begin == end) return PCT_OK;
+    pct_drop_opts oo = *o;
+    oo.block_end = end;
+    return hip_status(launch_drop(*plan, protons_dev(p), p->n, b, x, oo, ws, stream));
+}
+
+int pct_tv(const pct_plan *plan, const float *x, double eps, double *value_dev, float *grad, void *ws,
+           size_t ws_bytes, void *stream)
+{
+    if (!plan || !x || !value_dev || !finite_pos(eps)) return PCT_ERR_INVALID_ARG;
+    int st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    return hip_status(launch_tv(*plan, x, eps, value_dev, grad, ws, stream));
+}
+
+const char *pct_status_string(int status)
+{
+    switch (status) {
+    case PCT_OK: return "ok";
+    case PCT_ERR_INVALID_ARG: return "invalid argument";
+    case PCT_ERR_WORKSPACE: return "workspace missing, too small, misaligned or not uploaded";
+    case PCT_ERR_ROW_OVERFLOW: return "traced row longer than max_nnz";
+    case PCT_ERR_NONFINITE: return "non-finite input";
+    case PCT_ERR_REENTRY: return "voxel re-entry outside the kernel's window";
+    case PCT_ERR_HIP: return "HIP runtime error";
+    case PCT_ERR_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+int pct_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Internal declarations shared by the host entry points and the HIP kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "pct.h"
+
+namespace pct {
+
+// One table row per MLP vertex: c0t, c0th (mm), c2t, c2th (mm), u_k (mm), pad.
+constexpr int kRowDoubles = 8;
+constexpr int kMaxSegments = 1 << 16;
+constexpr int kMaxUploads = 16;
+
+// Geometry passed to kernels by value.
+struct GridDev {
+    int32_t n[3];
+    double pitch[3];
+    double lo[3];  // origin
+    double hi[3];  // origin + n*pitch
+};
+
+struct ProtonsDev {
+    const float *t_in, *v_in, *th_in, *ph_in, *t_out, *v_out, *th_out, *ph_out, *gantry;
+};
+
+// Workspace layout (byte offsets from the workspace base).
+struct Layout {
+    size_t hdr;      // status word and counters (256 B)
+    size_t table;    // (K+1) * kRowDoubles doubles
+    size_t acc;      // nvox * sizeof(dtype)
+    size_t cnt;      // nvox int32
+    size_t touched;  // nvox int32
+    size_t partial;  // kMaxPartials doubles
+    size_t total;
+};
+constexpr int kMaxPartials = 4096;
+
+// header words (uint32 index)
+enum : int { kHdrStatus = 0, kHdrTouched0 = 1, kHdrTouched1 = 2 };
+
+Layout layout_for(int64_t nvox, int K, int dtype);
+
+}  // namespace pct
+
+struct pct_plan {
+    pct_grid grid;
+    pct_mlp mlp;
+    int K;
+    int64_t nvox;
+    std::vector<double> table;  // (K+1) * kRowDoubles
+    void *uploaded[pct::kMaxUploads];
+    int n_uploaded;
+};
+
+namespace pct {
+
+// Launchers implemented in the HIP translation unit.  They assume validated
+// arguments and return a hipError_t value.
+int launch_trace(const pct_plan &pl, const ProtonsDev &p, int64_t first, int64_t count, int32_t max_nnz,
+                 int32_t *vox, double *chord, int32_t *nnz, void *ws, void *stream);
+int launch_forward(const pct_plan &pl, const ProtonsDev &p, int64_t n, const void *x, int dtype, void *y,
+                   void *nrm2, void *ws, void *stream);
+int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const void *r, int dtype, void *g,
+                       void *ws, void *stream);
+int launch_drop(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x,
+                const pct_drop_opts &o, void *ws, void *stream);
+int launch_tv(const pct_plan &pl, const float *x, double eps, double *value_dev, float *grad, void *ws,
+              void *stream);
+int upload_table(const pct_plan &pl, void *ws, void *stream);
+int read_status(const pct_plan &pl, void *ws, int reset, uint32_t *bits, void *stream);
+
+GridDev grid_dev(const pct_grid &g);
+
+}  // namespace pct

@@ -1,0 +1,261 @@
+// Device-side path machinery: MLP vertices from the coefficient table, the
+// per-segment voxel walk, consecutive-piece merging and the voxel re-entry
+// tracker that turns the piece stream into matrix-row semantics.
+//
+// Geometry is evaluated in FP64: on CDNA4 the vector FP64 FMA/add/mul rate
+// equals the (unpacked) FP32 rate, and FP64 keeps every plane-crossing
+// decision identical to an FP64 reference except on measure-zero ties.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pct_internal.h"
+
+namespace pct {
+
+struct Rec {
+    double t_in, v_in, th_in, ph_in, t_out, v_out, th_out, ph_out;
+    double cs, sn;  // cos, sin of the gantry angle
+};
+
+__device__ __forceinline__ Rec load_rec(const ProtonsDev &p, int64_t i)
+{
+    Rec r;
+    r.t_in = p.t_in[i];
+    r.v_in = p.v_in[i];
+    r.th_in = p.th_in[i];
+    r.ph_in = p.ph_in[i];
+    r.t_out = p.t_out[i];
+    r.v_out = p.v_out[i];
+    r.th_out = p.th_out[i];
+    r.ph_out = p.ph_out[i];
+    double phi = p.gantry[i];
+    sincos(phi, &r.sn, &r.cs);
+    return r;
+}
+
+__device__ __forceinline__ bool rec_finite(const Rec &r)
+{
+    return isfinite(r.t_in) && isfinite(r.v_in) && isfinite(r.th_in) && isfinite(r.ph_in) &&
+           isfinite(r.t_out) && isfinite(r.v_out) && isfinite(r.th_out) && isfinite(r.ph_out) &&
+           isfinite(r.cs) && isfinite(r.sn);
+}
+
+// Vertex k of the most likely path in lab coordinates (mm).  Row k of the
+// table gives t_k = c0t t_in + c0th th_in + c2t t_out + c2th th_out (same for
+// v) and the depth coordinate u_k.
+__device__ __forceinline__ void vertex(const Rec &r, const double *__restrict__ row, double P[3])
+{
+    const double c0t = row[0], c0h = row[1], c2t = row[2], c2h = row[3], u = row[4];
+    double t = c0t * r.t_in + c0h * r.th_in + c2t * r.t_out + c2h * r.th_out;
+    double v = c0t * r.v_in + c0h * r.ph_in + c2t * r.v_out + c2h * r.ph_out;
+    P[0] = u * r.cs - t * r.sn;
+    P[1] = u * r.sn + t * r.cs;
+    P[2] = v;
+}
+
+// Walk of one straight segment P0 -> P1 through the grid (Siddon's
+// parametrisation P0 + alpha (P1 - P0), alpha in [0, 1]).  Calls
+// sink.piece(ix, iy, iz, chord) for every sub-interval of positive length
+// inside the grid box, in path order.  Indices handed to the sink are always
+// inside the grid.
+template <class Sink>
+__device__ __forceinline__ void walk_segment(const double P0[3], const double P1[3], const GridDev &g, Sink &sink)
+{
+    double d[3], inv[3];
+    double a_lo = 0.0, a_hi = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d[a] = P1[a] - P0[a];
+        if (d[a] != 0.0) {
+            inv[a] = 1.0 / d[a];
+            double t0 = (g.lo[a] - P0[a]) * inv[a];
+            double t1 = (g.hi[a] - P0[a]) * inv[a];
+            a_lo = fmax(a_lo, fmin(t0, t1));
+            a_hi = fmin(a_hi, fmax(t0, t1));
+        } else {
+            inv[a] = 0.0;
+            if (!(P0[a] >= g.lo[a] && P0[a] < g.hi[a])) a_hi = -1.0;
+        }
+    }
+    if (!(a_lo < a_hi)) return;  // also rejects NaN
+    const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+
+    int idx[3], stp[3];
+    double anext[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double pos = P0[a] + a_lo * d[a];
+        double q = (pos - g.lo[a]) / g.pitch[a];
+        double f = floor(q);
+        int i = int(fmin(fmax(f, -1.0), double(g.n[a])));
+        if (d[a] < 0.0 && f == q) i -= 1;  // on a plane and moving down
+        i = min(max(i, 0), g.n[a] - 1);
+        idx[a] = i;
+        if (d[a] > 0.0) {
+            stp[a] = 1;
+            anext[a] = (g.lo[a] + (i + 1) * g.pitch[a] - P0[a]) * inv[a];
+        } else if (d[a] < 0.0) {
+            stp[a] = -1;
+            anext[a] = (g.lo[a] + i * g.pitch[a] - P0[a]) * inv[a];
+        } else {
+            stp[a] = 0;
+            anext[a] = 2.0;
+        }
+    }
+    double acur = a_lo;
+    const int max_it = g.n[0] + g.n[1] + g.n[2] + 4;
+    for (int it = 0; it < max_it; ++it) {
+        double am = fmin(fmin(anext[0], anext[1]), anext[2]);
+        double aend = fmin(am, a_hi);
+        if (aend > acur) sink.piece(idx[0], idx[1], idx[2], (aend - acur) * len);
+        if (!(am < a_hi)) break;
+        bool out = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (anext[a] == am) {
+                int i = idx[a] + stp[a];
+                out |= (i < 0) | (i >= g.n[a]);
+                idx[a] = i;
+                anext[a] = (g.lo[a] + (i + (stp[a] > 0 ? 1 : 0)) * g.pitch[a] - P0[a]) * inv[a];
+            }
+        }
+        if (out) break;
+        acur = fmax(acur, am);
+    }
+}
+
+// Walk of the whole polyline (K segments) of one proton.  `tab` rows are
+// kRowDoubles apart.  Also reports whether the path is monotone along the
+// dominant in-plane axis (needed by the re-entry tracker).
+template <class Sink>
+__device__ __forceinline__ void walk_path(const Rec &r, const double *__restrict__ tab, int K, const GridDev &g,
+                                          Sink &sink)
+{
+    double P0[3], P1[3];
+    vertex(r, tab, P0);
+    for (int k = 0; k < K; ++k) {
+        vertex(r, tab + (k + 1) * kRowDoubles, P1);
+        sink.segment(P1[0] - P0[0], P1[1] - P0[1]);
+        walk_segment(P0, P1, g, sink);
+        P0[0] = P1[0];
+        P0[1] = P1[1];
+        P0[2] = P1[2];
+    }
+}
+
+// Rounding of a chord to the solver's chord format: FP64 -> FP32 (RNE), then
+// to FP16 or BF16 (RNE).
+template <int CHORD>
+__device__ __forceinline__ double round_chord(double c)
+{
+    if constexpr (CHORD == PCT_CHORD_F64) {
+        return c;
+    } else {
+        float f = float(c);
+        if constexpr (CHORD == PCT_CHORD_F32) {
+            return double(f);
+        } else if constexpr (CHORD == PCT_CHORD_F16) {
+            _Float16 h = _Float16(f);
+            return double(float(h));
+        } else {
+            uint32_t u = __float_as_uint(f);
+            u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+            return double(__uint_as_float(u));
+        }
+    }
+}
+
+// Re-entry tracker.  A voxel can be visited again only while the path stays in
+// one slab of the dominant in-plane axis (the path is monotone along it), and
+// only after the index along one of the two other axes has reversed direction
+// inside that slab.  Until such a reversal every merged piece is a first visit;
+// afterwards pieces are looked up in a register window of the last R pieces.
+// If the window cannot cover the slab, or the path is not monotone along the
+// dominant axis, the proton is flagged (PCT_DEV_REENTRY).
+struct Reentry {
+    static constexpr int R = 4;
+    int dom;      // 0: x dominant, 1: y dominant
+    int dsign;    // direction of travel along the dominant axis
+    int cur_a, prev_b, prev_z, sgn_b, sgn_z, nslab;
+    bool rev, unsafe;
+    int rj[R];
+    double rc[R];
+
+    __device__ __forceinline__ void init(const Rec &r)
+    {
+        dom = fabs(r.cs) >= fabs(r.sn) ? 0 : 1;
+        double e = dom == 0 ? r.cs : r.sn;
+        dsign = e > 0.0 ? 1 : -1;
+        cur_a = -1;
+        prev_b = prev_z = 0;
+        sgn_b = sgn_z = 0;
+        nslab = 0;
+        rev = false;
+        unsafe = false;
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            rj[s] = -1;
+            rc[s] = 0.0;
+        }
+    }
+
+    __device__ __forceinline__ void segment(double dx, double dy)
+    {
+        double da = dom == 0 ? dx : dy;
+        if (!(da * dsign > 0.0)) unsafe = true;
+    }
+
+    // Registers merged piece (j, c); returns the sum of the chords of earlier
+    // pieces with the same voxel (0 on a first visit) and sets `first`.
+    __device__ __forceinline__ double visit(int j, int ix, int iy, int iz, double c, bool &first)
+    {
+        int ia = dom == 0 ? ix : iy;
+        int ib = dom == 0 ? iy : ix;
+        if (ia != cur_a) {
+            cur_a = ia;
+            sgn_b = sgn_z = 0;
+            rev = false;
+            nslab = 0;
+        } else {
+            int db = ib - prev_b, dz = iz - prev_z;
+            if (db != 0) {
+                int s = db > 0 ? 1 : -1;
+                if (sgn_b == 0) sgn_b = s;
+                else if (sgn_b != s) rev = true;
+            }
+            if (dz != 0) {
+                int s = dz > 0 ? 1 : -1;
+                if (sgn_z == 0) sgn_z = s;
+                else if (sgn_z != s) rev = true;
+            }
+        }
+        prev_b = ib;
+        prev_z = iz;
+        double aprev = 0.0;
+        first = true;
+        if (rev) {
+            if (nslab > R) unsafe = true;
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                if (rj[s] == j) {
+                    aprev += rc[s];
+                    first = false;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = R - 1; s > 0; --s) {
+            rj[s] = rj[s - 1];
+            rc[s] = rc[s - 1];
+        }
+        rj[0] = j;
+        rc[0] = c;
+        ++nslab;
+        return aprev;
+    }
+};
+
+}  // namespace pct

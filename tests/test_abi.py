@@ -1,0 +1,202 @@
+"""C-ABI contract tests that need no GPU: the library loads, exports every
+function include/pct.h declares, validates arguments on the host before any
+HIP call, and its host-side MLP table (Gauss-Legendre + Kalman-gain form)
+agrees with the oracle's (closed-form integrals + information form)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1802_01070_amd import _lib, synth
+from paper_1802_01070_amd.synth import Grid, MLPModel
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "pct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pct_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def plan_for(grid, mlp):
+    h = C.c_void_p()
+    st = _lib.lib().pct_plan_create(C.byref(_lib.make_grid(grid)), C.byref(_lib.make_mlp(mlp)), C.byref(h))
+    return st, h
+
+
+def table_of(h):
+    k = C.c_int32()
+    assert _lib.lib().pct_plan_segments(h, C.byref(k)) == 0
+    tab = np.zeros((k.value + 1) * 4)
+    assert _lib.lib().pct_plan_table(h, tab.ctypes.data_as(C.POINTER(C.c_double)), tab.size) == 0
+    return tab.reshape(-1, 4)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, "tiny"])
+def test_library_table_matches_oracle(cfg):
+    c = synth.CONFIGS[cfg]
+    st, h = plan_for(c.grid, c.mlp)
+    assert st == 0
+    got = table_of(h)
+    ref = oracle.mlp_table(c.mlp)
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got[:, 0], ref[:, 0], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(got[:, 2], ref[:, 2], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(got[:, 1], ref[:, 1], rtol=0, atol=1e-11)
+    np.testing.assert_allclose(got[:, 3], ref[:, 3], rtol=0, atol=1e-11)
+    _lib.lib().pct_plan_destroy(h)
+
+
+def test_library_table_odd_step_and_no_log_term():
+    for mlp in (MLPModel(u_in=-30, u_out=29.3, step=0.7), MLPModel(u_in=-100, u_out=100, log_term=0)):
+        st, h = plan_for(Grid(8, 8, 2), mlp)
+        assert st == 0
+        np.testing.assert_allclose(table_of(h), oracle.mlp_table(mlp), rtol=0, atol=1e-11)
+        _lib.lib().pct_plan_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(grid=Grid(0, 8, 2)),
+    dict(grid=Grid(8, 8, 2, pitch=(1.0, -1.0, 1.0))),
+    dict(grid=Grid(8, 8, 2, pitch=(1.0, float("nan"), 1.0))),
+    dict(grid=Grid(2048, 2048, 1024)),
+    dict(mlp=MLPModel(u_in=5, u_out=5)),
+    dict(mlp=MLPModel(u_in=-5, u_out=5, step=0.0)),
+    dict(mlp=MLPModel(u_in=-5, u_out=5, E0=-1.0)),
+    dict(mlp=MLPModel(u_in=-5, u_out=5, X0=0.0)),
+    dict(mlp=MLPModel(u_in=-5, u_out=5, log_term=2)),
+    dict(mlp=MLPModel(u_in=-1e9, u_out=1e9, step=1.0)),
+    dict(mlp=MLPModel(u_in=-5, u_out=5, poly=(-1.0, 0, 0, 0, 0, 0))),  # negative scattering power
+])
+def test_plan_create_rejects(bad):
+    grid = bad.get("grid", Grid(8, 8, 2))
+    mlp = bad.get("mlp", MLPModel(u_in=-5, u_out=5))
+    st, h = plan_for(grid, mlp)
+    assert st == -1
+    assert h.value is None
+
+
+def test_plan_create_null_args():
+    L = _lib.lib()
+    g = _lib.make_grid(Grid(8, 8, 2))
+    assert L.pct_plan_create(None, None, None) == -1
+    assert L.pct_plan_create(C.byref(g), None, C.byref(C.c_void_p())) == -1
+
+
+@pytest.fixture
+def plan():
+    st, h = plan_for(Grid(8, 8, 2), MLPModel(u_in=-5, u_out=5))
+    assert st == 0
+    yield h
+    _lib.lib().pct_plan_destroy(h)
+
+
+def fake_protons(n):
+    # non-null dummies: validation never dereferences them
+    return _lib.make_protons({k: 0x1000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, n)
+
+
+FAKE_WS = C.c_void_p(0x7F0000000000)  # 256-aligned, never uploaded
+
+
+def ws_size(h, dtype=0):
+    b = C.c_size_t()
+    assert _lib.lib().pct_workspace_size(h, 100, dtype, C.byref(b)) == 0
+    return b.value
+
+
+def test_workspace_size_rules(plan):
+    L = _lib.lib()
+    b = C.c_size_t()
+    assert L.pct_workspace_size(plan, -1, 0, C.byref(b)) == -1
+    assert L.pct_workspace_size(plan, 10, 7, C.byref(b)) == -1
+    assert ws_size(plan, 0) == ws_size(plan, 1)
+    assert ws_size(plan) >= 128 * 8 + 128 * 4 * 2
+
+
+def test_compute_calls_validate_before_device(plan):
+    L = _lib.lib()
+    p = fake_protons(100)
+    nb = ws_size(plan)
+    stream = None
+    # workspace missing / too small / misaligned / not uploaded
+    assert L.pct_forward(plan, C.byref(p), C.c_void_p(0x2000), 0, C.c_void_p(0x3000), None, None, nb, stream) == -2
+    assert L.pct_forward(plan, C.byref(p), C.c_void_p(0x2000), 0, C.c_void_p(0x3000), None, FAKE_WS, 16, stream) == -2
+    assert L.pct_forward(plan, C.byref(p), C.c_void_p(0x2000), 0, C.c_void_p(0x3000), None,
+                         C.c_void_p(0x7F0000000010), nb, stream) == -2
+    assert L.pct_forward(plan, C.byref(p), C.c_void_p(0x2000), 0, C.c_void_p(0x3000), None, FAKE_WS, nb, stream) == -2
+    # bad dtype, null x, negative n
+    assert L.pct_forward(plan, C.byref(p), C.c_void_p(0x2000), 5, C.c_void_p(0x3000), None, FAKE_WS, nb, stream) == -1
+    assert L.pct_forward(plan, C.byref(p), None, 0, C.c_void_p(0x3000), None, FAKE_WS, nb, stream) == -1
+    neg = fake_protons(-1)
+    assert L.pct_backproject(plan, C.byref(neg), C.c_void_p(1), 0, C.c_void_p(1), FAKE_WS, nb, stream) == -1
+    nullp = _lib.make_protons({k: 0 for k in _lib.FIELDS}, 10)
+    assert L.pct_backproject(plan, C.byref(nullp), C.c_void_p(1), 0, C.c_void_p(1), FAKE_WS, nb, stream) == -1
+    # trace ranges
+    tr = L.pct_mlp_trace
+    v = C.c_void_p(0x4000)
+    assert tr(plan, C.byref(p), 90, 20, 64, v, v, v, FAKE_WS, nb, stream) == -1     # past the end
+    assert tr(plan, C.byref(p), -1, 5, 64, v, v, v, FAKE_WS, nb, stream) == -1
+    assert tr(plan, C.byref(p), 0, 5, 0, v, v, v, FAKE_WS, nb, stream) == -1        # max_nnz
+    assert tr(plan, C.byref(p), 0, 5, 64, None, v, v, FAKE_WS, nb, stream) == -1
+    assert tr(plan, C.byref(p), 0, 5, 64, v, v, v, FAKE_WS, nb, stream) == -2       # not uploaded
+
+
+@pytest.mark.parametrize("field,value", [("block", 0), ("lambda_", 0.0), ("lambda_", float("inf")), ("n_iter", -1),
+                                         ("dtype", 3), ("chord", 9), ("flags", 0x80), ("block_begin", -1),
+                                         ("block_end", 2), ("block_begin", 3)])
+def test_drop_options_validated(plan, field, value):
+    L = _lib.lib()
+    p = fake_protons(100)
+    o = _lib.make_opts(64, 0.1, 1, 0)     # T = 2 blocks
+    setattr(o, field, value)
+    if field == "block_begin" and value == 3:
+        o.block_end = 1
+    if field == "block_end":
+        o.block_end = 3
+    st = L.pct_drop_iterate(plan, C.byref(p), C.c_void_p(0x5000), C.c_void_p(0x6000), C.byref(o), FAKE_WS,
+                            ws_size(plan), None)
+    assert st == -1, (field, value, st)
+
+
+def test_drop_valid_options_reach_workspace_check(plan):
+    L = _lib.lib()
+    p = fake_protons(100)
+    o = _lib.make_opts(64, 0.1, 1, 0)
+    st = L.pct_drop_iterate(plan, C.byref(p), C.c_void_p(0x5000), C.c_void_p(0x6000), C.byref(o), FAKE_WS,
+                            ws_size(plan), None)
+    assert st == -2
+
+
+def test_tv_validation(plan):
+    L = _lib.lib()
+    nb = ws_size(plan)
+    assert L.pct_tv(plan, None, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
+    assert L.pct_tv(plan, C.c_void_p(8), 0.0, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
+    assert L.pct_tv(plan, C.c_void_p(8), 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -2
+
+
+def test_status_strings():
+    for st in range(-7, 1):
+        s = _lib.status_string(st)
+        assert s and s != "unknown status"
+    assert _lib.status_string(-99) == "unknown status"
+
+
+def test_library_has_no_oracle_dependency():
+    # the product library must not link, load or name the oracle
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"orc_" not in data and b"liborc" not in data
