@@ -142,10 +142,15 @@ typedef struct {
     uint32_t flags;      /* PCT_DROP_* bits                                         */
     int64_t block_begin; /* first block of every sweep (>= 0)                       */
     int64_t block_end;   /* one past the last block; < 0 means ceil(n/B)            */
+    int32_t lanes;       /* lanes per proton in the block kernel: 0 automatic, or
+                            1, 8, 16, 32, 64                                         */
+    int32_t reserved;    /* must be 0                                              */
 } pct_drop_opts;
 
-#define PCT_DROP_CHECK_FINITE 0x1u /* scan records and b for NaN/Inf (device status) */
+#define PCT_DROP_CHECK_FINITE 0x1u /* reserved: records and b are always checked      */
 #define PCT_DROP_NO_GRAPH 0x2u     /* launch per block on the stream, no HIP graph   */
+#define PCT_DROP_PROFILE 0x4u      /* bracket a sample of the per-block kernels with
+                                      HIP events on `stream` (see pct_profile_read) */
 
 /* Workspace bytes for problems of this plan (n protons, x of type dtype). */
 int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes);
@@ -191,6 +196,13 @@ int pct_tv(const pct_plan *plan, const float *x, double eps, double *value_dev, 
            size_t ws_bytes, void *stream);
 
 /* ---- diagnostics --------------------------------------------------------- */
+
+/* Kernel timing of the last pct_drop_iterate call made with PCT_DROP_PROFILE:
+ * synchronises the recorded events and returns, per kernel kind (index 0: the
+ * fused block kernel, 1: the block commit), the summed duration in ms of the
+ * sampled launches and their number.  The plan keeps the events; profiling
+ * calls on one plan must not overlap. */
+int pct_profile_read(pct_plan *plan, double ms[2], int64_t launches[2]);
 const char *pct_status_string(int status);
 int pct_last_hip_error(void); /* hipError_t of the most recent PCT_ERR_HIP on this thread */
 

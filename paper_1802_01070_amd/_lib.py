@@ -17,12 +17,13 @@ PCT_F32, PCT_F64 = 0, 1
 CHORDS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 PCT_DROP_CHECK_FINITE = 0x1
 PCT_DROP_NO_GRAPH = 0x2
+PCT_DROP_PROFILE = 0x4
 DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry"}
 FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out", "gantry")
 
 EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan_table", "pct_workspace_size",
            "pct_plan_upload", "pct_device_status", "pct_mlp_trace", "pct_forward", "pct_backproject",
-           "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error")
+           "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read")
 
 
 class PctError(RuntimeError):
@@ -48,7 +49,7 @@ class pct_protons(C.Structure):
 class pct_drop_opts(C.Structure):
     _fields_ = [("block", C.c_int64), ("lambda_", C.c_double), ("n_iter", C.c_int32), ("dtype", C.c_int32),
                 ("chord", C.c_int32), ("flags", C.c_uint32), ("block_begin", C.c_int64),
-                ("block_end", C.c_int64)]
+                ("block_end", C.c_int64), ("lanes", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -77,6 +78,7 @@ def lib() -> C.CDLL:
             "pct_tv": ([vp, vp, C.c_double, vp, vp, vp, sz, vp], C.c_int),
             "pct_status_string": ([C.c_int], C.c_char_p),
             "pct_last_hip_error": ([], C.c_int),
+            "pct_profile_read": ([vp, P(C.c_double), P(i64)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -111,6 +113,6 @@ def make_protons(ptrs: dict, n: int) -> pct_protons:
 
 
 def make_opts(block: int, lam: float, n_iter: int, dtype: int, chord: str = "f64", flags: int = 0,
-              block_begin: int = 0, block_end: int = -1) -> pct_drop_opts:
+              block_begin: int = 0, block_end: int = -1, lanes: int = 0) -> pct_drop_opts:
     return pct_drop_opts(int(block), float(lam), int(n_iter), int(dtype), CHORDS[chord], int(flags),
-                         int(block_begin), int(block_end))
+                         int(block_begin), int(block_end), int(lanes), 0)

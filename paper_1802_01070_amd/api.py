@@ -146,11 +146,12 @@ def pct_backproject(plan: Plan, p: Protons, r: torch.Tensor, g: Optional[torch.T
 
 
 def pct_drop_iterate(plan: Plan, p: Protons, b: torch.Tensor, x: torch.Tensor, block: int, lam: float,
-                     n_iter: int, chord: str = "f64", flags: int = 0, block_begin: int = 0, block_end: int = -1):
+                     n_iter: int, chord: str = "f64", flags: int = 0, block_begin: int = 0, block_end: int = -1,
+                     lanes: int = 0):
     code = _dtype_code(x)
     bp = _dev(b, "b", dtype=torch.float32, numel=p.n)
     xp = _dev(x, "x", numel=plan.nvox)
-    o = _lib.make_opts(block, lam, n_iter, code, chord, flags, block_begin, block_end)
+    o = _lib.make_opts(block, lam, n_iter, code, chord, flags, block_begin, block_end, lanes)
     st = lib().pct_drop_iterate(plan.handle, C.byref(p.s), bp, xp, C.byref(o), plan.ws_ptr, plan.ws_bytes,
                                 _stream(x.device))
     check(st, "pct_drop_iterate")
@@ -166,6 +167,15 @@ def pct_tv(plan: Plan, x: torch.Tensor, eps: float, with_grad: bool = True):
                       _stream(x.device))
     check(st, "pct_tv")
     return val, grad
+
+
+def pct_profile_read(plan: Plan):
+    """(ms, launches) per kernel kind [fused block kernel, commit] of the last
+    profiled pct_drop_iterate call."""
+    ms = (C.c_double * 2)()
+    n = (C.c_int64 * 2)()
+    check(lib().pct_profile_read(plan.handle, ms, n), "pct_profile_read")
+    return [ms[0], ms[1]], [n[0], n[1]]
 
 
 def pct_device_status(plan: Plan, reset: bool = True) -> int:

@@ -36,8 +36,6 @@ Layout layout_for(int64_t nvox, int K, int dtype)
     off = align256(off + size_t(nvox) * vsize);
     L.cnt = off;
     off = align256(off + size_t(nvox) * sizeof(int32_t));
-    L.touched = off;
-    off = align256(off + size_t(nvox) * sizeof(int32_t));
     L.partial = off;
     off = align256(off + size_t(kMaxPartials) * sizeof(double));
     L.total = off;
@@ -227,6 +225,9 @@ int pct_plan_create(const pct_grid *grid, const pct_mlp *mlp, pct_plan **out)
     if (pl->K < 1) pl->K = 1;
     pl->nvox = int64_t(grid->nx) * grid->ny * grid->nz;
     pl->n_uploaded = 0;
+    pl->prof_used[0] = pl->prof_used[1] = 0;
+    pl->graph_exec = nullptr;
+    pl->capture_stream = nullptr;
     if (!build_table(*pl)) {
         delete pl;
         return PCT_ERR_INVALID_ARG;
@@ -235,7 +236,13 @@ int pct_plan_create(const pct_grid *grid, const pct_mlp *mlp, pct_plan **out)
     return PCT_OK;
 }
 
-void pct_plan_destroy(pct_plan *plan) { delete plan; }
+void pct_plan_destroy(pct_plan *plan)
+{
+    if (!plan) return;
+    profile_release(*plan);
+    graph_release(*plan);
+    delete plan;
+}
 
 int pct_plan_segments(const pct_plan *plan, int32_t *K)
 {
@@ -338,8 +345,11 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (p->n > 0 && !b) return PCT_ERR_INVALID_ARG;
     if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
     if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
-    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH)) return PCT_ERR_INVALID_ARG;
+    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE)) return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
+    if (o->lanes != 0 && o->lanes != 1 && o->lanes != 8 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64)
+        return PCT_ERR_INVALID_ARG;
+    if (o->reserved != 0) return PCT_ERR_INVALID_ARG;
     int64_t T = p->n > 0 ? (p->n + o->block - 1) / o->block : 0;
     int64_t end = o->block_end < 0 ? T : o->block_end;
     if (o->block_begin < 0 || end > T || o->block_begin > end) return PCT_ERR_INVALID_ARG;
@@ -348,7 +358,7 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->n_iter == 0 || o->block_begin == end) return PCT_OK;
     pct_drop_opts oo = *o;
     oo.block_end = end;
-    return hip_status(launch_drop(*plan, protons_dev(p), p->n, b, x, oo, ws, stream));
+    return hip_status(launch_drop(*const_cast<pct_plan *>(plan), protons_dev(p), p->n, b, x, oo, ws, stream));
 }
 
 int pct_tv(const pct_plan *plan, const float *x, double eps, double *value_dev, float *grad, void *ws,
@@ -376,5 +386,11 @@ const char *pct_status_string(int status)
 }
 
 int pct_last_hip_error(void) { return g_last_hip_error; }
+
+int pct_profile_read(pct_plan *plan, double ms[2], int64_t launches[2])
+{
+    if (!plan || !ms || !launches) return PCT_ERR_INVALID_ARG;
+    return hip_status(profile_read(*plan, ms, launches));
+}
 
 }  // extern "C"

@@ -32,14 +32,14 @@ struct Layout {
     size_t table;    // (K+1) * kRowDoubles doubles
     size_t acc;      // nvox * sizeof(dtype)
     size_t cnt;      // nvox int32
-    size_t touched;  // nvox int32
     size_t partial;  // kMaxPartials doubles
     size_t total;
 };
 constexpr int kMaxPartials = 4096;
 
-// header words (uint32 index)
-enum : int { kHdrStatus = 0, kHdrTouched0 = 1, kHdrTouched1 = 2 };
+// header words (int32 index): status word, then the [jmin, jmax] voxel range
+// touched by a block, double-buffered by block parity
+enum : int { kHdrStatus = 0, kHdrRange0 = 2, kHdrRange1 = 4 };
 
 Layout layout_for(int64_t nvox, int K, int dtype);
 
@@ -53,6 +53,13 @@ struct pct_plan {
     std::vector<double> table;  // (K+1) * kRowDoubles
     void *uploaded[pct::kMaxUploads];
     int n_uploaded;
+    // profiling events (hipEvent_t), pairs per sampled launch and kernel kind
+    std::vector<void *> prof_events[2];
+    int prof_used[2];
+    // instantiated graph of one DROP sweep (hipGraphExec_t) and its launch key
+    void *graph_exec;
+    std::vector<uint64_t> graph_key;
+    void *capture_stream;  // private hipStream_t used only to record the graph
 };
 
 namespace pct {
@@ -65,11 +72,14 @@ int launch_forward(const pct_plan &pl, const ProtonsDev &p, int64_t n, const voi
                    void *nrm2, void *ws, void *stream);
 int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const void *r, int dtype, void *g,
                        void *ws, void *stream);
-int launch_drop(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x,
+int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x,
                 const pct_drop_opts &o, void *ws, void *stream);
 int launch_tv(const pct_plan &pl, const float *x, double eps, double *value_dev, float *grad, void *ws,
               void *stream);
 int upload_table(const pct_plan &pl, void *ws, void *stream);
+int profile_read(pct_plan &pl, double ms[2], int64_t launches[2]);
+void profile_release(pct_plan &pl);
+void graph_release(pct_plan &pl);
 int read_status(const pct_plan &pl, void *ws, int reset, uint32_t *bits, void *stream);
 
 GridDev grid_dev(const pct_grid &g);

@@ -3,14 +3,19 @@
 //   k_trace        ordered emission list of each proton's path (debug/parity)
 //   k_forward      y = A x, ||a_i||^2   (one lane per proton, gathers)
 //   k_backproject  g += A^T r           (one lane per proton, atomics)
-//   k_drop_rows    DROP block: walk -> a_i.x, ||a_i||^2 -> rho_i -> re-walk and
-//                  scatter rho_i a_ij into the block accumulator and the
-//                  per-voxel row count, first touch appends to a touched list
-//   k_drop_commit  x_j += acc_j / s_j over the touched list, reset
+//   k_drop_block   DROP block, LPP lanes per proton: walk -> a_i.x, ||a_i||^2 ->
+//                  rho_i -> re-walk and scatter rho_i a_ij into the block
+//                  accumulator and the per-voxel row count; records the
+//                  block's touched voxel index range
+//   k_drop_rows    the same with one lane per proton (very long paths)
+//   k_drop_commit  x_j += acc_j / s_j over the touched range, reset
 //   k_tv           smoothed total variation value and gradient
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
+#include <cstring>
+#include <vector>
 
 #include "pct_internal.h"
 #include "pct_path.hpp"
@@ -179,38 +184,248 @@ template <typename T>
 struct DropScatterSink {
     T *acc;
     int32_t *cnt;
-    int32_t *touched;
-    unsigned *ntouched;
     Reentry re;
     double rho;
+    int jmin, jmax;
     __device__ __forceinline__ void segment(double dx, double dy) { re.segment(dx, dy); }
     __device__ __forceinline__ void final(int j, int ix, int iy, int iz, double c)
     {
         bool first;
         re.visit(j, ix, iy, iz, c, first);
         atomicAdd(acc + j, T(rho * c));
-        if (first) {
-            int old = atomicAdd(cnt + j, 1);
-            if (old == 0) touched[atomicAdd(ntouched, 1u)] = j;
-        }
+        if (first) atomicAdd(cnt + j, 1);
+        jmin = min(jmin, j);
+        jmax = max(jmax, j);
     }
 };
 
+// Workgroup-wide min/max of the touched voxel range, then one atomic pair per
+// workgroup into the block's range words.  Every thread of the workgroup must
+// call it.
+__device__ __forceinline__ void publish_range(int jmin, int jmax, int *range)
+{
+    __shared__ int smin[kWG / 64], smax[kWG / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        jmin = min(jmin, __shfl_xor(jmin, off, 64));
+        jmax = max(jmax, __shfl_xor(jmax, off, 64));
+    }
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        smin[w] = jmin;
+        smax[w] = jmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = smin[0], b = smax[0];
+        for (int q = 1; q < int(blockDim.x / 64); ++q) {
+            a = min(a, smin[q]);
+            b = max(b, smax[q]);
+        }
+        if (b >= a) {
+            atomicMin(range, a);
+            atomicMax(range + 1, b);
+        }
+    }
+}
+
 template <typename T, int CHORD>
 __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__restrict__ b,
-                                                   const T *__restrict__ x, T *acc, int32_t *cnt, int32_t *touched,
-                                                   unsigned *ntouched, const double *__restrict__ tab, int K,
-                                                   GridDev g, int64_t lo, int64_t hi, double lambda,
-                                                   unsigned *status)
+                                                   const T *__restrict__ x, T *acc, int32_t *cnt, int *range,
+                                                   const double *__restrict__ tab, int K, GridDev g, int64_t lo,
+                                                   int64_t hi, double lambda, unsigned *status)
 {
     int64_t i = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= hi) return;
-    Rec r = load_rec(p, i);
-    double bi = double(b[i]);
-    if (!rec_finite(r) || !isfinite(bi)) {
-        raise_status(status, PCT_DEV_NONFINITE);
-        return;
+    bool active = i < hi;
+    Rec r{};
+    double bi = 0.0;
+    if (active) {
+        r = load_rec(p, i);
+        bi = double(b[i]);
+        if (!rec_finite(r) || !isfinite(bi)) {
+            raise_status(status, PCT_DEV_NONFINITE);
+            active = false;
+        }
     }
+    DropScatterSink<T> sc;
+    sc.jmin = INT_MAX;
+    sc.jmax = -1;
+    if (active) {
+        DotSink<T> s;
+        s.x = x;
+        s.dot = 0.0;
+        s.n2 = 0.0;
+        s.re.init(r);
+        {
+            Merge<DotSink<T>, CHORD> m(s, g);
+            walk_path(r, tab, K, g, m);
+            m.finish();
+        }
+        if (s.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
+        if (s.n2 > 0.0) {
+            sc.acc = acc;
+            sc.cnt = cnt;
+            sc.rho = lambda * (bi - s.dot) / s.n2;
+            sc.re.init(r);
+            Merge<DropScatterSink<T>, CHORD> m(sc, g);
+            walk_path(r, tab, K, g, m);
+            m.finish();
+        }
+    }
+    publish_range(sc.jmin, sc.jmax, range);
+}
+
+// ---------------------------------------------------------------------------
+// DROP block kernel, LPP lanes per proton.
+//
+// The path is monotone along its dominant in-plane axis (the lab axis closest
+// to the beam direction), so a voxel can only be visited again while the path
+// stays inside one slab of that axis.  The slabs the path crosses are split
+// into LPP contiguous ranges, one per lane; each lane walks the pieces of the
+// path inside its range.  Lanes therefore never share a voxel: merging,
+// re-entry tracking, ||a_i||^2 and the once-per-row count stay lane-local, and
+// the only cross-lane step is the sum of a_i.x and ||a_i||^2.
+//
+// Per proton: the dominant coordinate of every vertex is staged in LDS (one
+// value per vertex, computed by the group's lanes in parallel); it gives the
+// monotonicity check and, by binary search, each lane's first segment.  A path
+// that is not monotone falls back to a single-lane walk of the whole row.
+// ---------------------------------------------------------------------------
+template <int LPP>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int LPP>
+__device__ __forceinline__ bool group_any(bool p)
+{
+    int v = p ? 1 : 0;
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, 64);
+    return v != 0;
+}
+
+// Lane's share of the path: dominant-axis index range [s0, s1] (s0 > s1: none)
+// and first segment.
+struct LaneRange {
+    int dom, s0, s1, k0;
+    bool full;  // single-lane fallback: walk every segment over the whole grid
+};
+
+template <int LPP>
+__device__ __forceinline__ LaneRange lane_range(const Rec &r, const double *__restrict__ tab, int K, const GridDev &g,
+                                                double *__restrict__ A, int l, bool active)
+{
+    LaneRange lr;
+    lr.dom = fabs(r.cs) >= fabs(r.sn) ? 0 : 1;
+    const double e = lr.dom == 0 ? r.cs : r.sn;
+    const double sgn = e > 0.0 ? 1.0 : -1.0;
+    // stage the signed dominant coordinate of every vertex
+    for (int k = l; k <= K; k += LPP) A[k] = active ? sgn * vertex_axis(r, tab + k * kRowDoubles, lr.dom) : 0.0;
+    __syncthreads();
+    bool bad = false;
+    for (int k = l; k < K; k += LPP) bad |= !(A[k + 1] > A[k]);
+    bad = group_any<LPP>(bad);
+    lr.full = bad;
+    lr.k0 = 0;
+    if (bad) {
+        lr.s0 = 0;
+        lr.s1 = l == 0 ? g.n[lr.dom] - 1 : -1;
+        return lr;
+    }
+    // index range crossed by the path (the path spans [A[0], A[K]] in signed
+    // coordinate), clamped to the grid
+    const int a = lr.dom;
+    double c0 = sgn * A[0], c1 = sgn * A[K];
+    double cmin = fmin(c0, c1), cmax = fmax(c0, c1);
+    double f0 = floor((cmin - g.lo[a]) / g.pitch[a]);
+    double f1 = floor((cmax - g.lo[a]) / g.pitch[a]);
+    int i0 = int(fmin(fmax(f0, 0.0), double(g.n[a] - 1)));
+    int i1 = int(fmin(fmax(f1, 0.0), double(g.n[a] - 1)));
+    if (f1 < 0.0 || f0 > double(g.n[a] - 1)) {
+        lr.s0 = 0;
+        lr.s1 = -1;
+        return lr;
+    }
+    const int ns = i1 - i0 + 1;
+    const int q = ns / LPP, rem = ns % LPP;
+    // lanes take ranges in the direction of travel
+    const int off = l * q + min(l, rem);
+    const int cntl = q + (l < rem ? 1 : 0);
+    if (sgn > 0.0) {
+        lr.s0 = i0 + off;
+        lr.s1 = lr.s0 + cntl - 1;
+    } else {
+        lr.s1 = i1 - off;
+        lr.s0 = lr.s1 - cntl + 1;
+    }
+    if (cntl <= 0) return lr;
+    // entry boundary of the lane's range in signed coordinate
+    const double entry = sgn > 0.0 ? g.lo[a] + lr.s0 * g.pitch[a] : -(g.lo[a] + (lr.s1 + 1) * g.pitch[a]);
+    // last vertex k in [0, K-1] with A[k] <= entry (A increasing)
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (A[mid] <= entry) lo = mid;
+        else hi = mid - 1;
+    }
+    lr.k0 = lo;
+    return lr;
+}
+
+// Walks the lane's share of the path, feeding `m` (a Merge sink).
+template <class M>
+__device__ __forceinline__ void walk_lane(const Rec &r, const double *__restrict__ tab, int K, const GridDev &g,
+                                          const LaneRange &lr, const double *__restrict__ A, M &m)
+{
+    if (lr.s0 > lr.s1) return;
+    const int a = lr.dom;
+    const double sgn = (a == 0 ? r.cs : r.sn) > 0.0 ? 1.0 : -1.0;
+    // exit boundary of the lane's range in signed coordinate
+    const double exitc = sgn > 0.0 ? g.lo[a] + (lr.s1 + 1) * g.pitch[a] : -(g.lo[a] + lr.s0 * g.pitch[a]);
+    double P0[3], P1[3];
+    vertex(r, tab + lr.k0 * kRowDoubles, P0);
+    for (int k = lr.k0; k < K; ++k) {
+        vertex(r, tab + (k + 1) * kRowDoubles, P1);
+        m.segment(P1[0] - P0[0], P1[1] - P0[1]);
+        walk_segment_range(P0, P1, g, a, lr.s0, lr.s1, m);
+        if (!lr.full && A[k + 1] >= exitc) break;
+        P0[0] = P1[0];
+        P0[1] = P1[1];
+        P0[2] = P1[2];
+    }
+}
+
+template <typename T, int CHORD, int LPP>
+__global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *__restrict__ b,
+                                                    const T *__restrict__ x, T *acc, int32_t *cnt, int *range,
+                                                    const double *__restrict__ tab, int K, GridDev g, int64_t lo,
+                                                    int64_t hi, double lambda, unsigned *status)
+{
+    extern __shared__ double lds_A[];
+    constexpr int GPB = kWG / LPP;  // proton groups per workgroup
+    const int grp = threadIdx.x / LPP;
+    const int l = threadIdx.x % LPP;
+    const int64_t i = lo + int64_t(blockIdx.x) * GPB + grp;
+    bool active = i < hi;
+    Rec r{};
+    double bi = 0.0;
+    if (active) {
+        r = load_rec(p, i);
+        bi = double(b[i]);
+        if (!rec_finite(r) || !isfinite(bi)) {
+            if (l == 0) raise_status(status, PCT_DEV_NONFINITE);
+            active = false;
+        }
+    }
+    if (!active) r.cs = 1.0, r.sn = 0.0;
+    double *A = lds_A + grp * (K + 1);
+    LaneRange lr = lane_range<LPP>(r, tab, K, g, A, l, active);
+    if (!active) lr.s1 = lr.s0 - 1;
+
     DotSink<T> s;
     s.x = x;
     s.dot = 0.0;
@@ -218,43 +433,58 @@ __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__
     s.re.init(r);
     {
         Merge<DotSink<T>, CHORD> m(s, g);
-        walk_path(r, tab, K, g, m);
+        walk_lane(r, tab, K, g, lr, A, m);
         m.finish();
     }
     if (s.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
-    if (!(s.n2 > 0.0)) return;
+    const double dot = group_sum<LPP>(s.dot);
+    const double n2 = group_sum<LPP>(s.n2);
     DropScatterSink<T> sc;
-    sc.acc = acc;
-    sc.cnt = cnt;
-    sc.touched = touched;
-    sc.ntouched = ntouched;
-    sc.rho = lambda * (bi - s.dot) / s.n2;
-    sc.re.init(r);
-    Merge<DropScatterSink<T>, CHORD> m(sc, g);
-    walk_path(r, tab, K, g, m);
-    m.finish();
+    sc.jmin = INT_MAX;
+    sc.jmax = -1;
+    if (n2 > 0.0) {
+        sc.acc = acc;
+        sc.cnt = cnt;
+        sc.rho = lambda * (bi - dot) / n2;
+        sc.re.init(r);
+        Merge<DropScatterSink<T>, CHORD> m(sc, g);
+        walk_lane(r, tab, K, g, lr, A, m);
+        m.finish();
+    }
+    publish_range(sc.jmin, sc.jmax, range);
 }
 
+// Commit of one block: a dense, coalesced scan of the block's touched index
+// range; voxels with a non-zero row count get x_j += acc_j / s_j and are reset.
+// Also re-arms the range words of the next block.
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_drop_commit(T *x, T *acc, int32_t *cnt, const int32_t *__restrict__ touched,
-                                                     const unsigned *ntouched_this, unsigned *ntouched_next)
+__global__ void __launch_bounds__(kWG) k_drop_commit(T *x, T *acc, int32_t *cnt, const int *range_this,
+                                                     int *range_next)
 {
-    const unsigned n = *ntouched_this;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ntouched_next = 0u;
-    for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        int j = touched[q];
-        double s = double(cnt[j]);
-        x[j] = T(double(x[j]) + double(acc[j]) / s);
-        acc[j] = T(0);
-        cnt[j] = 0;
+    const int j0 = range_this[0], j1 = range_this[1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        range_next[0] = INT_MAX;
+        range_next[1] = -1;
+    }
+    if (j1 < j0 || j0 < 0) return;  // nothing touched
+    const int stride = int(gridDim.x * blockDim.x);
+    for (int j = j0 + int(blockIdx.x * blockDim.x + threadIdx.x); j <= j1; j += stride) {
+        const int c = cnt[j];
+        if (c != 0) {
+            x[j] = T(double(x[j]) + double(acc[j]) / double(c));
+            acc[j] = T(0);
+            cnt[j] = 0;
+        }
     }
 }
 
-__global__ void k_reset_counters(unsigned *hdr)
+__global__ void k_reset_ranges(int *hdr)
 {
     if (threadIdx.x == 0) {
-        hdr[kHdrTouched0] = 0u;
-        hdr[kHdrTouched1] = 0u;
+        hdr[kHdrRange0] = INT_MAX;
+        hdr[kHdrRange0 + 1] = -1;
+        hdr[kHdrRange1] = INT_MAX;
+        hdr[kHdrRange1 + 1] = -1;
     }
 }
 
@@ -407,37 +637,205 @@ int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const
     return hipGetLastError();
 }
 
+// Profiling: a pool of event pairs per kernel kind; launches are sampled
+// evenly so that at most kProfSamples pairs are recorded per call.
+constexpr int kProfSamples = 512;
+
+static hipError_t prof_prepare(pct_plan &pl)
+{
+    for (int k = 0; k < 2; ++k) {
+        pl.prof_used[k] = 0;
+        while (pl.prof_events[k].size() < size_t(2 * kProfSamples)) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            pl.prof_events[k].push_back(e);
+        }
+    }
+    return hipSuccess;
+}
+
+static inline hipEvent_t prof_event(pct_plan &pl, int kind, int idx)
+{
+    return static_cast<hipEvent_t>(pl.prof_events[kind][idx]);
+}
+
+int profile_read(pct_plan &pl, double ms[2], int64_t launches[2])
+{
+    for (int k = 0; k < 2; ++k) {
+        ms[k] = 0.0;
+        launches[k] = pl.prof_used[k];
+        for (int i = 0; i < pl.prof_used[k]; ++i) {
+            hipEvent_t a = prof_event(pl, k, 2 * i), b = prof_event(pl, k, 2 * i + 1);
+            hipError_t e = hipEventSynchronize(b);
+            if (e != hipSuccess) return e;
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, a, b);
+            if (e != hipSuccess) return e;
+            ms[k] += t;
+        }
+    }
+    return hipSuccess;
+}
+
+void profile_release(pct_plan &pl)
+{
+    for (int k = 0; k < 2; ++k) {
+        for (void *e : pl.prof_events[k]) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+        pl.prof_events[k].clear();
+        pl.prof_used[k] = 0;
+    }
+}
+
+// Launch of one block's fused kernel with the chosen lanes per proton.
 template <typename T, int CHORD>
-static int drop_loop(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
+static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, T *x, T *acc, int32_t *cnt,
+                         int *range, const double *tab, int K, const GridDev &g, int64_t lo, int64_t hi,
+                         double lambda, unsigned *status)
+{
+    const int64_t n = hi - lo;
+    switch (lanes) {
+#define PCT_LAUNCH_LPP(LPP)                                                                                      \
+    case LPP: {                                                                                                  \
+        const unsigned grid = unsigned((n + (kWG / LPP) - 1) / (kWG / LPP));                                  \
+        const size_t lds = size_t(kWG / LPP) * size_t(K + 1) * sizeof(double);                               \
+        hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP>), dim3(grid), dim3(kWG), lds, s, p, b, x, acc, cnt,      \
+                           range, tab, K, g, lo, hi, lambda, status);                                             \
+        break;                                                                                                   \
+    }
+        PCT_LAUNCH_LPP(8)
+        PCT_LAUNCH_LPP(16)
+        PCT_LAUNCH_LPP(32)
+        PCT_LAUNCH_LPP(64)
+#undef PCT_LAUNCH_LPP
+    default:
+        hipLaunchKernelGGL((k_drop_rows<T, CHORD>), dim3(grid_for(n)), dim3(kWG), 0, s, p, b, x, acc, cnt, range,
+                           tab, K, g, lo, hi, lambda, status);
+    }
+}
+
+// Lanes per proton: enough lanes that each walks a few slabs of the dominant
+// axis, within the LDS budget of the staged vertex coordinates.
+static int choose_lanes(const pct_plan &pl, int requested)
+{
+    constexpr size_t kLdsBudget = 64 * 1024;
+    int lanes = requested;
+    if (lanes == 0) {
+        const int ndom = std::max(pl.grid.nx, pl.grid.ny);
+        lanes = ndom >= 160 ? 64 : ndom >= 64 ? 32 : 16;
+    }
+    if (lanes > 1 && size_t(kWG / lanes) * size_t(pl.K + 1) * sizeof(double) > kLdsBudget) lanes = 1;
+    return lanes;
+}
+
+void graph_release(pct_plan &pl)
+{
+    if (pl.graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(pl.graph_exec));
+    pl.graph_exec = nullptr;
+    pl.graph_key.clear();
+    if (pl.capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(pl.capture_stream));
+    pl.capture_stream = nullptr;
+}
+
+template <typename T, int CHORD>
+static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
                      const pct_drop_opts &o, void *ws, hipStream_t s)
 {
+    const bool prof = (o.flags & PCT_DROP_PROFILE) != 0;
+    if (prof) {
+        hipError_t e = prof_prepare(pl);
+        if (e != hipSuccess) return e;
+    }
+    const int lanes = choose_lanes(pl, o.lanes);
+    const int64_t nblk = o.block_end - o.block_begin;
+    const int64_t every = std::max<int64_t>(1, (nblk + kProfSamples - 1) / kProfSamples);
     Layout L = layout_for(pl.nvox, pl.K, o.dtype);
     const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
-    unsigned *hdr = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr);
+    unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
+    int *hdr = reinterpret_cast<int *>(wsb(ws) + L.hdr);
     T *acc = reinterpret_cast<T *>(wsb(ws) + L.acc);
     int32_t *cnt = reinterpret_cast<int32_t *>(wsb(ws) + L.cnt);
-    int32_t *touched = reinterpret_cast<int32_t *>(wsb(ws) + L.touched);
     GridDev g = grid_dev(pl.grid);
-    const unsigned commit_grid = unsigned(std::min<int64_t>(1024, (pl.nvox + kWG - 1) / kWG));
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, hdr);
-    int64_t seq = 0;
-    for (int it = 0; it < o.n_iter; ++it) {
+    const unsigned commit_grid = unsigned(std::min<int64_t>(4096, (pl.nvox + kWG - 1) / kWG));
+
+    // One sweep: re-arm the range words, then block kernel + commit per block.
+    // Profiling samples one sweep's launches evenly.
+    auto enqueue_sweep = [&](hipStream_t s, bool record_events) {
+        hipLaunchKernelGGL(k_reset_ranges, dim3(1), dim3(64), 0, s, hdr);
+        int64_t seq = 0;
         for (int64_t t = o.block_begin; t < o.block_end; ++t, ++seq) {
             int64_t lo = t * o.block;
             int64_t hi = std::min<int64_t>(n, lo + o.block);
-            unsigned *nt_this = hdr + (seq % 2 == 0 ? kHdrTouched0 : kHdrTouched1);
-            unsigned *nt_next = hdr + (seq % 2 == 0 ? kHdrTouched1 : kHdrTouched0);
-            hipLaunchKernelGGL((k_drop_rows<T, CHORD>), dim3(grid_for(hi - lo)), dim3(kWG), 0, s, p, b, x, acc, cnt,
-                               touched, nt_this, tab, pl.K, g, lo, hi, o.lambda, hdr + kHdrStatus);
-            hipLaunchKernelGGL(k_drop_commit<T>, dim3(commit_grid), dim3(kWG), 0, s, x, acc, cnt, touched, nt_this,
-                               nt_next);
+            int *r_this = hdr + (seq % 2 == 0 ? kHdrRange0 : kHdrRange1);
+            int *r_next = hdr + (seq % 2 == 0 ? kHdrRange1 : kHdrRange0);
+            const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
+            if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
+            launch_block<T, CHORD>(lanes, s, p, b, x, acc, cnt, r_this, tab, pl.K, g, lo, hi, o.lambda, status);
+            if (sample) {
+                (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
+                pl.prof_used[0]++;
+                (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1]), s);
+            }
+            hipLaunchKernelGGL(k_drop_commit<T>, dim3(commit_grid), dim3(kWG), 0, s, x, acc, cnt, r_this, r_next);
+            if (sample) {
+                (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1] + 1), s);
+                pl.prof_used[1]++;
+            }
         }
+    };
+
+    const bool use_graph = !(o.flags & PCT_DROP_NO_GRAPH) && !prof;
+    if (!use_graph) {
+        for (int it = 0; it < o.n_iter; ++it) enqueue_sweep(s, prof && it == o.n_iter - 1);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    // The sweep is captured once into a HIP graph and replayed; the graph is
+    // cached on the plan for identical launch arguments.
+    std::vector<uint64_t> key = {
+        reinterpret_cast<uint64_t>(p.t_in),   reinterpret_cast<uint64_t>(p.v_in),
+        reinterpret_cast<uint64_t>(p.th_in),  reinterpret_cast<uint64_t>(p.ph_in),
+        reinterpret_cast<uint64_t>(p.t_out),  reinterpret_cast<uint64_t>(p.v_out),
+        reinterpret_cast<uint64_t>(p.th_out), reinterpret_cast<uint64_t>(p.ph_out),
+        reinterpret_cast<uint64_t>(p.gantry), reinterpret_cast<uint64_t>(b),
+        reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
+        uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
+        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), 0};
+    std::memcpy(&key.back(), &o.lambda, sizeof(double));
+    if (!pl.graph_exec || pl.graph_key != key) {
+        // recorded on a private stream (the caller's stream may be the null
+        // stream, which cannot be captured); launched on the caller's stream
+        if (pl.graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(pl.graph_exec));
+        pl.graph_exec = nullptr;
+        pl.graph_key.clear();
+        if (!pl.capture_stream) {
+            hipStream_t cs = nullptr;
+            hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+            pl.capture_stream = cs;
+        }
+        hipStream_t cs = static_cast<hipStream_t>(pl.capture_stream);
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        enqueue_sweep(cs, false);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        if (e != hipSuccess) return e;
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        pl.graph_exec = exec;
+        pl.graph_key = key;
+    }
+    for (int it = 0; it < o.n_iter; ++it) {
+        hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(pl.graph_exec), s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T>
-static int drop_dispatch_chord(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
+static int drop_dispatch_chord(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
                                const pct_drop_opts &o, void *ws, hipStream_t s)
 {
     switch (o.chord) {
@@ -448,7 +846,7 @@ static int drop_dispatch_chord(const pct_plan &pl, const ProtonsDev &p, int64_t 
     }
 }
 
-int launch_drop(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x, const pct_drop_opts &o,
+int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x, const pct_drop_opts &o,
                 void *ws, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);

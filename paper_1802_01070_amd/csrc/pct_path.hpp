@@ -56,28 +56,52 @@ __device__ __forceinline__ void vertex(const Rec &r, const double *__restrict__ 
     P[2] = v;
 }
 
-// Walk of one straight segment P0 -> P1 through the grid (Siddon's
-// parametrisation P0 + alpha (P1 - P0), alpha in [0, 1]).  Calls
-// sink.piece(ix, iy, iz, chord) for every sub-interval of positive length
-// inside the grid box, in path order.  Indices handed to the sink are always
-// inside the grid.
-template <class Sink>
-__device__ __forceinline__ void walk_segment(const double P0[3], const double P1[3], const GridDev &g, Sink &sink)
+// Coordinate of vertex k along lab axis `dom` (0: x, 1: y), evaluated with the
+// same expressions as vertex().
+__device__ __forceinline__ double vertex_axis(const Rec &r, const double *__restrict__ row, int dom)
 {
-    double d[3], inv[3];
+    const double c0t = row[0], c0h = row[1], c2t = row[2], c2h = row[3], u = row[4];
+    double t = c0t * r.t_in + c0h * r.th_in + c2t * r.t_out + c2h * r.th_out;
+    return dom == 0 ? u * r.cs - t * r.sn : u * r.sn + t * r.cs;
+}
+
+// Walk of one straight segment P0 -> P1 through the part of the grid whose
+// index along axis `ra` lies in [r_lo, r_hi] (Siddon's parametrisation
+// P0 + alpha (P1 - P0), alpha in [0, 1]).  Calls sink.piece(ix, iy, iz, chord)
+// for every sub-interval of positive length inside that box, in path order.
+// The box faces along `ra` are grid planes, so the pieces are exactly the
+// pieces of the full walk that fall in the index range.  Indices handed to
+// the sink are always inside the grid.
+template <class Sink>
+__device__ __forceinline__ void walk_segment_range(const double P0[3], const double P1[3], const GridDev &g,
+                                                   int ra, int r_lo, int r_hi, Sink &sink)
+{
+    double d[3], inv[3], lo[3], hi[3];
+    int ilo[3], ihi[3];
     double a_lo = 0.0, a_hi = 1.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+        if (a == ra) {
+            ilo[a] = r_lo;
+            ihi[a] = r_hi;
+            lo[a] = g.lo[a] + r_lo * g.pitch[a];
+            hi[a] = g.lo[a] + (r_hi + 1) * g.pitch[a];
+        } else {
+            ilo[a] = 0;
+            ihi[a] = g.n[a] - 1;
+            lo[a] = g.lo[a];
+            hi[a] = g.hi[a];
+        }
         d[a] = P1[a] - P0[a];
         if (d[a] != 0.0) {
             inv[a] = 1.0 / d[a];
-            double t0 = (g.lo[a] - P0[a]) * inv[a];
-            double t1 = (g.hi[a] - P0[a]) * inv[a];
+            double t0 = (lo[a] - P0[a]) * inv[a];
+            double t1 = (hi[a] - P0[a]) * inv[a];
             a_lo = fmax(a_lo, fmin(t0, t1));
             a_hi = fmin(a_hi, fmax(t0, t1));
         } else {
             inv[a] = 0.0;
-            if (!(P0[a] >= g.lo[a] && P0[a] < g.hi[a])) a_hi = -1.0;
+            if (!(P0[a] >= lo[a] && P0[a] < hi[a])) a_hi = -1.0;
         }
     }
     if (!(a_lo < a_hi)) return;  // also rejects NaN
@@ -92,7 +116,7 @@ __device__ __forceinline__ void walk_segment(const double P0[3], const double P1
         double f = floor(q);
         int i = int(fmin(fmax(f, -1.0), double(g.n[a])));
         if (d[a] < 0.0 && f == q) i -= 1;  // on a plane and moving down
-        i = min(max(i, 0), g.n[a] - 1);
+        i = min(max(i, ilo[a]), ihi[a]);
         idx[a] = i;
         if (d[a] > 0.0) {
             stp[a] = 1;
@@ -117,7 +141,7 @@ __device__ __forceinline__ void walk_segment(const double P0[3], const double P1
         for (int a = 0; a < 3; ++a) {
             if (anext[a] == am) {
                 int i = idx[a] + stp[a];
-                out |= (i < 0) | (i >= g.n[a]);
+                out |= (i < ilo[a]) | (i > ihi[a]);
                 idx[a] = i;
                 anext[a] = (g.lo[a] + (i + (stp[a] > 0 ? 1 : 0)) * g.pitch[a] - P0[a]) * inv[a];
             }
@@ -125,6 +149,12 @@ __device__ __forceinline__ void walk_segment(const double P0[3], const double P1
         if (out) break;
         acur = fmax(acur, am);
     }
+}
+
+template <class Sink>
+__device__ __forceinline__ void walk_segment(const double P0[3], const double P1[3], const GridDev &g, Sink &sink)
+{
+    walk_segment_range(P0, P1, g, 0, 0, g.n[0] - 1, sink);
 }
 
 // Walk of the whole polyline (K segments) of one proton.  `tab` rows are
