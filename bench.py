@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--protons", type=int, default=0, help="override the number of protons")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=320)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per proton in the block kernel (0: automatic)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -110,7 +111,7 @@ def main():
 
     # untimed warmup sweeps (the first run also compiles nothing: the library is prebuilt)
     for _ in range(args.warmup):
-        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1)
+        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes)
     torch.cuda.synchronize()
     x.fill_(1.0)
     torch.cuda.synchronize()
@@ -122,15 +123,18 @@ def main():
     e0.record(stream)
     t_host = time.perf_counter()
     for k in range(args.steps):
-        # the last timed step brackets a sample of the block kernels with HIP
-        # events on this same stream (library-side) to time the dominant kernel
-        flags = PCT_DROP_PROFILE if k == args.steps - 1 else 0
-        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, flags=flags)
+        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes)
         log(f"[bench] step {k + 1}/{args.steps} enqueued")
     e1.record(stream)
     torch.cuda.synchronize()
     t_host = time.perf_counter() - t_host
     ms_total = e0.elapsed_time(e1)
+    # One more sweep, right after the timed region and on the same stream, with
+    # a sample of the block-kernel and commit launches bracketed by HIP events
+    # (recorded by the library) to time the dominant kernel itself.
+    api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes,
+                         flags=PCT_DROP_PROFILE)
+    torch.cuda.synchronize()
     bits = api.pct_device_status(plan)
     if bits:
         log(f"[bench] WARNING device status {bits:#x}")
@@ -173,7 +177,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_drop_block (fused MLP trace + a.x + |a|^2 + rho + D-weighted scatter), 64 lanes per proton",
+            "kernel": "k_drop_block (fused MLP trace + a.x + |a|^2 + rho + D-weighted scatter)",
+            "lanes_per_proton": args.lanes or "auto",
             "kernel_avg_us": k_avg_ms * 1e3,
             "kernel_launches_sampled": k_n,
             "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -186,7 +191,7 @@ def main():
     if not args.no_cpu_baseline:
         nb = min(args.cpu_blocks, T)
         xs = torch.ones(sc.grid.nvox, dtype=vdtype, device=dev)
-        api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1, block_end=nb)
+        api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1, block_end=nb, lanes=args.lanes)
         torch.cuda.synchronize()
         log(f"[bench] CPU oracle baseline on {nb} blocks ...")
         cb, emax, emean = cpu_baseline(sc, cfg, xs.double().cpu().numpy(), nb)

@@ -71,6 +71,7 @@ extern "C" {
 #define PCT_DEV_ROW_OVERFLOW 0x1u
 #define PCT_DEV_NONFINITE 0x2u
 #define PCT_DEV_REENTRY 0x4u
+#define PCT_DEV_ACC_RANGE 0x8u /* a DROP contribution beyond the FP32 accumulator's fixed-point range */
 
 /* ---- value and chord types --------------------------------------------- */
 typedef enum {
@@ -137,7 +138,11 @@ typedef struct {
     int64_t block;       /* protons per block B, > 0                                */
     double lambda;       /* relaxation, finite, > 0                                 */
     int32_t n_iter;      /* sweeps over all blocks, >= 0                            */
-    int32_t dtype;       /* pct_dtype of x (accumulators use the same type)         */
+    int32_t dtype;       /* pct_dtype of x.  FP64: FP64 block accumulator and count;
+                            FP32: one 64-bit word per voxel with the row count and
+                            the block sum in 2^-28 fixed point (order-independent,
+                            so results are bitwise reproducible); |block sum| must
+                            stay below 2^15 (PCT_DEV_ACC_RANGE otherwise)          */
     int32_t chord;       /* pct_chord                                               */
     uint32_t flags;      /* PCT_DROP_* bits                                         */
     int64_t block_begin; /* first block of every sweep (>= 0)                       */
@@ -148,6 +153,7 @@ typedef struct {
 } pct_drop_opts;
 
 #define PCT_DROP_CHECK_FINITE 0x1u /* reserved: records and b are always checked      */
+/* B must be below 2^20 (the packed count field) for the FP32 value type. */
 #define PCT_DROP_NO_GRAPH 0x2u     /* launch per block on the stream, no HIP graph   */
 #define PCT_DROP_PROFILE 0x4u      /* bracket a sample of the per-block kernels with
                                       HIP events on `stream` (see pct_profile_read) */

@@ -18,7 +18,7 @@ CHORDS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 PCT_DROP_CHECK_FINITE = 0x1
 PCT_DROP_NO_GRAPH = 0x2
 PCT_DROP_PROFILE = 0x4
-DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry"}
+DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range"}
 FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out", "gantry")
 
 EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan_table", "pct_workspace_size",

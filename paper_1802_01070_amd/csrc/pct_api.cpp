@@ -347,6 +347,7 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
     if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE)) return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
+    if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 20)) return PCT_ERR_INVALID_ARG;
     if (o->lanes != 0 && o->lanes != 1 && o->lanes != 8 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64)
         return PCT_ERR_INVALID_ARG;
     if (o->reserved != 0) return PCT_ERR_INVALID_ARG;

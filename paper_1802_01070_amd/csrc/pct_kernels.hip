@@ -180,10 +180,45 @@ __global__ void __launch_bounds__(kWG) k_backproject(ProtonsDev p, int64_t n, co
 // ---------------------------------------------------------------------------
 // DROP
 // ---------------------------------------------------------------------------
+// Block accumulator for the FP32 value type: one 64-bit word per voxel holding
+// the number of block rows that touch the voxel (bits 63..44) and the sum of
+// rho_i a_ij in fixed point with kFixBits fractional bits (two's complement in
+// the low bits).  One integer atomic per piece updates both, and integer
+// addition makes the block sum independent of the order of the atomics.  The
+// sum must stay below 2^(43 - kFixBits) in magnitude; larger single
+// contributions are clamped and raise PCT_DEV_ACC_RANGE.
+constexpr int kFixBits = 28;
+constexpr int kCntShift = 44;
+constexpr double kFixScale = double(1u << kFixBits);
+constexpr double kFixMax = double(1u << 12);
+
+__device__ __forceinline__ unsigned long long pack_contribution(double v, bool first, unsigned *status)
+{
+    if (!(fabs(v) < kFixMax)) {
+        atomicOr(status, PCT_DEV_ACC_RANGE);
+        v = fmin(fmax(v, -kFixMax), kFixMax);
+        if (v != v) v = 0.0;
+    }
+    const long long q = llrint(v * kFixScale);
+    return static_cast<unsigned long long>(q) + (first ? (1ull << kCntShift) : 0ull);
+}
+
+__device__ __forceinline__ void unpack_accumulator(unsigned long long w, int &cnt, double &sum)
+{
+    const long long W = static_cast<long long>(w);
+    const long long c = (W + (1ll << (kCntShift - 1))) >> kCntShift;
+    const long long V = W - (c << kCntShift);
+    cnt = int(c);
+    sum = double(V) * (1.0 / kFixScale);
+}
+
+// Scatter of one row: acc_j += rho a_ij and s_j += 1 once per row.  FP32 value
+// type: packed 64-bit accumulator; FP64: double accumulator plus int count.
 template <typename T>
 struct DropScatterSink {
-    T *acc;
+    void *acc;
     int32_t *cnt;
+    unsigned *status;
     Reentry re;
     double rho;
     int jmin, jmax;
@@ -192,8 +227,12 @@ struct DropScatterSink {
     {
         bool first;
         re.visit(j, ix, iy, iz, c, first);
-        atomicAdd(acc + j, T(rho * c));
-        if (first) atomicAdd(cnt + j, 1);
+        if constexpr (sizeof(T) == 4) {
+            atomicAdd(static_cast<unsigned long long *>(acc) + j, pack_contribution(rho * c, first, status));
+        } else {
+            atomicAdd(static_cast<double *>(acc) + j, rho * c);
+            if (first) atomicAdd(cnt + j, 1);
+        }
         jmin = min(jmin, j);
         jmax = max(jmax, j);
     }
@@ -222,16 +261,18 @@ __device__ __forceinline__ void publish_range(int jmin, int jmax, int *range)
             a = min(a, smin[q]);
             b = max(b, smax[q]);
         }
+        // same-address atomics serialise across the chip: only issue the ones
+        // that can still move the extremes (they only ever tighten)
         if (b >= a) {
-            atomicMin(range, a);
-            atomicMax(range + 1, b);
+            if (a < __hip_atomic_load(range, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(range, a);
+            if (b > __hip_atomic_load(range + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(range + 1, b);
         }
     }
 }
 
 template <typename T, int CHORD>
 __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__restrict__ b,
-                                                   const T *__restrict__ x, T *acc, int32_t *cnt, int *range,
+                                                   const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
                                                    const double *__restrict__ tab, int K, GridDev g, int64_t lo,
                                                    int64_t hi, double lambda, unsigned *status)
 {
@@ -265,6 +306,7 @@ __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__
         if (s.n2 > 0.0) {
             sc.acc = acc;
             sc.cnt = cnt;
+            sc.status = status;
             sc.rho = lambda * (bi - s.dot) / s.n2;
             sc.re.init(r);
             Merge<DropScatterSink<T>, CHORD> m(sc, g);
@@ -401,7 +443,7 @@ __device__ __forceinline__ void walk_lane(const Rec &r, const double *__restrict
 
 template <typename T, int CHORD, int LPP>
 __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *__restrict__ b,
-                                                    const T *__restrict__ x, T *acc, int32_t *cnt, int *range,
+                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
                                                     const double *__restrict__ tab, int K, GridDev g, int64_t lo,
                                                     int64_t hi, double lambda, unsigned *status)
 {
@@ -445,6 +487,7 @@ __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *_
     if (n2 > 0.0) {
         sc.acc = acc;
         sc.cnt = cnt;
+        sc.status = status;
         sc.rho = lambda * (bi - dot) / n2;
         sc.re.init(r);
         Merge<DropScatterSink<T>, CHORD> m(sc, g);
@@ -458,7 +501,7 @@ __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *_
 // range; voxels with a non-zero row count get x_j += acc_j / s_j and are reset.
 // Also re-arms the range words of the next block.
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_drop_commit(T *x, T *acc, int32_t *cnt, const int *range_this,
+__global__ void __launch_bounds__(kWG) k_drop_commit(T *x, void *accv, int32_t *cnt, const int *range_this,
                                                      int *range_next)
 {
     const int j0 = range_this[0], j1 = range_this[1];
@@ -469,11 +512,24 @@ __global__ void __launch_bounds__(kWG) k_drop_commit(T *x, T *acc, int32_t *cnt,
     if (j1 < j0 || j0 < 0) return;  // nothing touched
     const int stride = int(gridDim.x * blockDim.x);
     for (int j = j0 + int(blockIdx.x * blockDim.x + threadIdx.x); j <= j1; j += stride) {
-        const int c = cnt[j];
-        if (c != 0) {
-            x[j] = T(double(x[j]) + double(acc[j]) / double(c));
-            acc[j] = T(0);
-            cnt[j] = 0;
+        if constexpr (sizeof(T) == 4) {
+            unsigned long long *pk = static_cast<unsigned long long *>(accv);
+            const unsigned long long w = pk[j];
+            if (w != 0ull) {
+                int c;
+                double sum;
+                unpack_accumulator(w, c, sum);
+                if (c > 0) x[j] = T(double(x[j]) + sum / double(c));
+                pk[j] = 0ull;
+            }
+        } else {
+            double *acc = static_cast<double *>(accv);
+            const int c = cnt[j];
+            if (c != 0) {
+                x[j] = T(double(x[j]) + acc[j] / double(c));
+                acc[j] = 0.0;
+                cnt[j] = 0;
+            }
         }
     }
 }
@@ -689,7 +745,7 @@ void profile_release(pct_plan &pl)
 
 // Launch of one block's fused kernel with the chosen lanes per proton.
 template <typename T, int CHORD>
-static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, T *x, T *acc, int32_t *cnt,
+static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, T *x, void *acc, int32_t *cnt,
                          int *range, const double *tab, int K, const GridDev &g, int64_t lo, int64_t hi,
                          double lambda, unsigned *status)
 {
@@ -753,7 +809,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
     const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
     unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
     int *hdr = reinterpret_cast<int *>(wsb(ws) + L.hdr);
-    T *acc = reinterpret_cast<T *>(wsb(ws) + L.acc);
+    void *acc = wsb(ws) + L.acc;
     int32_t *cnt = reinterpret_cast<int32_t *>(wsb(ws) + L.cnt);
     GridDev g = grid_dev(pl.grid);
     const unsigned commit_grid = unsigned(std::min<int64_t>(4096, (pl.nvox + kWG - 1) / kWG));

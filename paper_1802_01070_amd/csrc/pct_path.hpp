@@ -177,7 +177,9 @@ __device__ __forceinline__ void walk_path(const Rec &r, const double *__restrict
 }
 
 // Rounding of a chord to the solver's chord format: FP64 -> FP32 (RNE), then
-// to FP16 or BF16 (RNE).
+// to FP16 or BF16 (RNE).  The second step works on the FP32 bit pattern: a
+// plain half(float(c)) may be folded by the compiler into one direct
+// FP64 -> FP16 rounding, which differs from the two-step rounding on FP16 ties.
 template <int CHORD>
 __device__ __forceinline__ double round_chord(double c)
 {
@@ -188,8 +190,14 @@ __device__ __forceinline__ double round_chord(double c)
         if constexpr (CHORD == PCT_CHORD_F32) {
             return double(f);
         } else if constexpr (CHORD == PCT_CHORD_F16) {
-            _Float16 h = _Float16(f);
-            return double(float(h));
+            if (fabsf(f) < 0x1p-14f) {
+                // FP16 subnormal range: fixed quantum 2^-24 (scaling by powers of
+                // two is exact; rintf rounds to nearest even)
+                return double(rintf(f * 0x1p24f) * 0x1p-24f);
+            }
+            uint32_t u = __float_as_uint(f);
+            u = (u + 0x0FFFu + ((u >> 13) & 1u)) & 0xFFFFE000u;  // keep 10 mantissa bits
+            return double(fminf(__uint_as_float(u), 65504.0f));
         } else {
             uint32_t u = __float_as_uint(f);
             u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;

@@ -445,3 +445,25 @@ def test_graph_replays_match_eager():
     side.synchronize()
     assert (x2 - eager).abs().max().item() <= 1e-12
     assert_status_clean(plan)
+
+
+def test_fp32_drop_is_bitwise_reproducible():
+    # the FP32 block accumulator is integer (fixed point + count), so repeated
+    # runs and a split resume give identical bits
+    c = synth.CONFIGS[2]
+    sc = scan(2, 64000)
+    plan, pr = gpu_setup(sc)
+    b = torch.from_numpy(sc.b).to(DEV)
+    runs = []
+    for _ in range(3):
+        x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+        api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=2)
+        runs.append(x)
+    x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+    api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_end=7)
+    api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_begin=7)
+    api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1)
+    runs.append(x)
+    for r in runs[1:]:
+        assert torch.equal(runs[0], r)
+    assert_status_clean(plan)

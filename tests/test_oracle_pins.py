@@ -425,7 +425,14 @@ def test_drop_block_range_resume_is_exact():
 # ---------------------------------------------------------------------------
 def test_chord_rounding_matches_numpy_formats():
     rng = np.random.default_rng(9)
-    vals = np.concatenate([rng.uniform(0, 1.8, 2000), rng.uniform(0, 1e-4, 200), [0.0, 1.0, 0.5 + 2 ** -12]])
+    # exact FP16 and BF16 ties (FP32 values halfway between two representable
+    # neighbours), values just off a tie, and FP16 subnormal-range chords
+    ties16 = [(1 + (2 * k + 1) * 2.0 ** -11) * 2.0 ** e for k in range(0, 1024, 37) for e in (-3, -1, 0)]
+    ties_bf = [(1 + (2 * k + 1) * 2.0 ** -8) * 2.0 ** e for k in range(0, 128, 5) for e in (-3, 0)]
+    near = [t * (1 + 2.0 ** -30) for t in ties16[:20]] + [t * (1 - 2.0 ** -30) for t in ties16[:20]]
+    sub = [k * 2.0 ** -25 for k in range(1, 60)] + list(rng.uniform(0, 6e-5, 100))
+    vals = np.concatenate([rng.uniform(0, 1.8, 2000), rng.uniform(0, 1e-4, 200), [0.0, 1.0, 0.5 + 2 ** -12],
+                           ties16, ties_bf, near, sub])
     for c in vals:
         f = float(np.float32(c))
         assert oracle.round_chord(c, "f32") == f
