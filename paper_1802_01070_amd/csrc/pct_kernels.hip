@@ -350,94 +350,102 @@ __device__ __forceinline__ bool group_any(bool p)
     return v != 0;
 }
 
-// Lane's share of the path: dominant-axis index range [s0, s1] (s0 > s1: none)
-// and first segment.
-struct LaneRange {
-    int dom, s0, s1, k0;
-    bool full;  // single-lane fallback: walk every segment over the whole grid
+// Per-proton path state shared by the LPP lanes of its group, in LDS: the lab
+// coordinates of every vertex (P, 3 per vertex) and the signed coordinate of
+// every vertex along the dominant axis (A, increasing along the path).
+struct GroupPath {
+    int dom;      // dominant in-plane axis (0: x, 1: y)
+    double sgn;   // direction of travel along it
+    int s_lo, s_hi;  // dominant-axis index range crossed by the path (s_lo > s_hi: none)
+    bool full;    // not monotone: lane 0 walks the whole row over the whole grid
 };
 
 template <int LPP>
-__device__ __forceinline__ LaneRange lane_range(const Rec &r, const double *__restrict__ tab, int K, const GridDev &g,
-                                                double *__restrict__ A, int l, bool active)
+__device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__restrict__ tab, int K,
+                                                const GridDev &g, double *__restrict__ P, double *__restrict__ A,
+                                                int l, bool active)
 {
-    LaneRange lr;
-    lr.dom = fabs(r.cs) >= fabs(r.sn) ? 0 : 1;
-    const double e = lr.dom == 0 ? r.cs : r.sn;
-    const double sgn = e > 0.0 ? 1.0 : -1.0;
-    // stage the signed dominant coordinate of every vertex
-    for (int k = l; k <= K; k += LPP) A[k] = active ? sgn * vertex_axis(r, tab + k * kRowDoubles, lr.dom) : 0.0;
+    GroupPath gp;
+    gp.dom = fabs(r.cs) >= fabs(r.sn) ? 0 : 1;
+    const double e = gp.dom == 0 ? r.cs : r.sn;
+    gp.sgn = e > 0.0 ? 1.0 : -1.0;
+    for (int k = l; k <= K; k += LPP) {
+        double v[3] = {0.0, 0.0, 0.0};
+        if (active) vertex(r, tab + k * kRowDoubles, v);
+        P[3 * k] = v[0];
+        P[3 * k + 1] = v[1];
+        P[3 * k + 2] = v[2];
+        A[k] = gp.sgn * v[gp.dom];
+    }
     __syncthreads();
-    bool bad = false;
+    bool bad = !active;
     for (int k = l; k < K; k += LPP) bad |= !(A[k + 1] > A[k]);
-    bad = group_any<LPP>(bad);
-    lr.full = bad;
-    lr.k0 = 0;
-    if (bad) {
-        lr.s0 = 0;
-        lr.s1 = l == 0 ? g.n[lr.dom] - 1 : -1;
-        return lr;
+    gp.full = group_any<LPP>(bad);
+    gp.s_lo = 0;
+    gp.s_hi = -1;
+    if (gp.full) {
+        if (active) gp.s_hi = g.n[gp.dom] - 1;
+        return gp;
     }
-    // index range crossed by the path (the path spans [A[0], A[K]] in signed
-    // coordinate), clamped to the grid
-    const int a = lr.dom;
-    double c0 = sgn * A[0], c1 = sgn * A[K];
-    double cmin = fmin(c0, c1), cmax = fmax(c0, c1);
-    double f0 = floor((cmin - g.lo[a]) / g.pitch[a]);
-    double f1 = floor((cmax - g.lo[a]) / g.pitch[a]);
-    int i0 = int(fmin(fmax(f0, 0.0), double(g.n[a] - 1)));
-    int i1 = int(fmin(fmax(f1, 0.0), double(g.n[a] - 1)));
-    if (f1 < 0.0 || f0 > double(g.n[a] - 1)) {
-        lr.s0 = 0;
-        lr.s1 = -1;
-        return lr;
+    const int a = gp.dom;
+    const double c0 = gp.sgn * A[0], c1 = gp.sgn * A[K];
+    const double f0 = floor((fmin(c0, c1) - g.lo[a]) / g.pitch[a]);
+    const double f1 = floor((fmax(c0, c1) - g.lo[a]) / g.pitch[a]);
+    if (f1 < 0.0 || f0 > double(g.n[a] - 1)) return gp;
+    gp.s_lo = int(fmax(f0, 0.0));
+    gp.s_hi = int(fmin(f1, double(g.n[a] - 1)));
+    return gp;
+}
+
+// Walks the pieces of the path inside dominant-axis slab `s` (or, for a
+// non-monotone path, every segment over the whole grid), feeding `m`.
+template <class M>
+__device__ __forceinline__ void walk_slab(const GroupPath &gp, int s, int K, const GridDev &g,
+                                          const double *__restrict__ P, const double *__restrict__ A, M &m)
+{
+    const int a = gp.dom;
+    if (gp.full) {
+        for (int k = 0; k < K; ++k) {
+            const double *p0 = P + 3 * k, *p1 = P + 3 * k + 3;
+            m.segment(p1[0] - p0[0], p1[1] - p0[1]);
+            walk_segment_range(p0, p1, g, a, 0, g.n[a] - 1, m);
+        }
+        return;
     }
-    const int ns = i1 - i0 + 1;
-    const int q = ns / LPP, rem = ns % LPP;
-    // lanes take ranges in the direction of travel
-    const int off = l * q + min(l, rem);
-    const int cntl = q + (l < rem ? 1 : 0);
-    if (sgn > 0.0) {
-        lr.s0 = i0 + off;
-        lr.s1 = lr.s0 + cntl - 1;
-    } else {
-        lr.s1 = i1 - off;
-        lr.s0 = lr.s1 - cntl + 1;
-    }
-    if (cntl <= 0) return lr;
-    // entry boundary of the lane's range in signed coordinate
-    const double entry = sgn > 0.0 ? g.lo[a] + lr.s0 * g.pitch[a] : -(g.lo[a] + (lr.s1 + 1) * g.pitch[a]);
-    // last vertex k in [0, K-1] with A[k] <= entry (A increasing)
+    // entry and exit planes of the slab in signed coordinate
+    const double lo_pl = g.lo[a] + s * g.pitch[a], hi_pl = g.lo[a] + (s + 1) * g.pitch[a];
+    const double entry = gp.sgn > 0.0 ? lo_pl : -hi_pl;
+    const double exitc = gp.sgn > 0.0 ? hi_pl : -lo_pl;
+    // last vertex k in [0, K-1] with A[k] <= entry
     int lo = 0, hi = K - 1;
     while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
+        const int mid = (lo + hi + 1) >> 1;
         if (A[mid] <= entry) lo = mid;
         else hi = mid - 1;
     }
-    lr.k0 = lo;
-    return lr;
+    for (int k = lo; k < K; ++k) {
+        const double *p0 = P + 3 * k, *p1 = P + 3 * k + 3;
+        m.segment(p1[0] - p0[0], p1[1] - p0[1]);
+        walk_segment_range(p0, p1, g, a, s, s, m);
+        if (A[k + 1] >= exitc) break;
+    }
 }
 
-// Walks the lane's share of the path, feeding `m` (a Merge sink).
-template <class M>
-__device__ __forceinline__ void walk_lane(const Rec &r, const double *__restrict__ tab, int K, const GridDev &g,
-                                          const LaneRange &lr, const double *__restrict__ A, M &m)
+// The slabs of a lane: s_lo + l, s_lo + l + LPP, ...  Interleaving the lanes
+// over consecutive slabs keeps the voxels a wave touches at one step close
+// together along the path.
+template <int LPP, class M>
+__device__ __forceinline__ void walk_lane(const GroupPath &gp, int l, int K, const GridDev &g,
+                                          const double *__restrict__ P, const double *__restrict__ A, M &m)
 {
-    if (lr.s0 > lr.s1) return;
-    const int a = lr.dom;
-    const double sgn = (a == 0 ? r.cs : r.sn) > 0.0 ? 1.0 : -1.0;
-    // exit boundary of the lane's range in signed coordinate
-    const double exitc = sgn > 0.0 ? g.lo[a] + (lr.s1 + 1) * g.pitch[a] : -(g.lo[a] + lr.s0 * g.pitch[a]);
-    double P0[3], P1[3];
-    vertex(r, tab + lr.k0 * kRowDoubles, P0);
-    for (int k = lr.k0; k < K; ++k) {
-        vertex(r, tab + (k + 1) * kRowDoubles, P1);
-        m.segment(P1[0] - P0[0], P1[1] - P0[1]);
-        walk_segment_range(P0, P1, g, a, lr.s0, lr.s1, m);
-        if (!lr.full && A[k + 1] >= exitc) break;
-        P0[0] = P1[0];
-        P0[1] = P1[1];
-        P0[2] = P1[2];
+    if (gp.full) {
+        if (l == 0 && gp.s_hi >= gp.s_lo) walk_slab(gp, 0, K, g, P, A, m);
+        return;
+    }
+    if (gp.sgn > 0.0) {
+        for (int s = gp.s_lo + l; s <= gp.s_hi; s += LPP) walk_slab(gp, s, K, g, P, A, m);
+    } else {
+        for (int s = gp.s_hi - l; s >= gp.s_lo; s -= LPP) walk_slab(gp, s, K, g, P, A, m);
     }
 }
 
@@ -447,7 +455,7 @@ __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *_
                                                     const double *__restrict__ tab, int K, GridDev g, int64_t lo,
                                                     int64_t hi, double lambda, unsigned *status)
 {
-    extern __shared__ double lds_A[];
+    extern __shared__ double lds[];
     constexpr int GPB = kWG / LPP;  // proton groups per workgroup
     const int grp = threadIdx.x / LPP;
     const int l = threadIdx.x % LPP;
@@ -464,9 +472,9 @@ __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *_
         }
     }
     if (!active) r.cs = 1.0, r.sn = 0.0;
-    double *A = lds_A + grp * (K + 1);
-    LaneRange lr = lane_range<LPP>(r, tab, K, g, A, l, active);
-    if (!active) lr.s1 = lr.s0 - 1;
+    double *P = lds + grp * 4 * (K + 1);
+    double *A = P + 3 * (K + 1);
+    const GroupPath gp = stage_path<LPP>(r, tab, K, g, P, A, l, active);
 
     DotSink<T> s;
     s.x = x;
@@ -475,7 +483,7 @@ __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *_
     s.re.init(r);
     {
         Merge<DotSink<T>, CHORD> m(s, g);
-        walk_lane(r, tab, K, g, lr, A, m);
+        walk_lane<LPP>(gp, l, K, g, P, A, m);
         m.finish();
     }
     if (s.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
@@ -491,7 +499,7 @@ __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *_
         sc.rho = lambda * (bi - dot) / n2;
         sc.re.init(r);
         Merge<DropScatterSink<T>, CHORD> m(sc, g);
-        walk_lane(r, tab, K, g, lr, A, m);
+        walk_lane<LPP>(gp, l, K, g, P, A, m);
         m.finish();
     }
     publish_range(sc.jmin, sc.jmax, range);
@@ -754,7 +762,7 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
 #define PCT_LAUNCH_LPP(LPP)                                                                                      \
     case LPP: {                                                                                                  \
         const unsigned grid = unsigned((n + (kWG / LPP) - 1) / (kWG / LPP));                                  \
-        const size_t lds = size_t(kWG / LPP) * size_t(K + 1) * sizeof(double);                               \
+        const size_t lds = size_t(kWG / LPP) * 4 * size_t(K + 1) * sizeof(double);                           \
         hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP>), dim3(grid), dim3(kWG), lds, s, p, b, x, acc, cnt,      \
                            range, tab, K, g, lo, hi, lambda, status);                                             \
         break;                                                                                                   \
@@ -780,7 +788,7 @@ static int choose_lanes(const pct_plan &pl, int requested)
         const int ndom = std::max(pl.grid.nx, pl.grid.ny);
         lanes = ndom >= 160 ? 64 : ndom >= 64 ? 32 : 16;
     }
-    if (lanes > 1 && size_t(kWG / lanes) * size_t(pl.K + 1) * sizeof(double) > kLdsBudget) lanes = 1;
+    if (lanes > 1 && size_t(kWG / lanes) * 4 * size_t(pl.K + 1) * sizeof(double) > kLdsBudget) lanes = 1;
     return lanes;
 }
 

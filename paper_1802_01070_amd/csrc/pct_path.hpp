@@ -56,14 +56,6 @@ __device__ __forceinline__ void vertex(const Rec &r, const double *__restrict__ 
     P[2] = v;
 }
 
-// Coordinate of vertex k along lab axis `dom` (0: x, 1: y), evaluated with the
-// same expressions as vertex().
-__device__ __forceinline__ double vertex_axis(const Rec &r, const double *__restrict__ row, int dom)
-{
-    const double c0t = row[0], c0h = row[1], c2t = row[2], c2h = row[3], u = row[4];
-    double t = c0t * r.t_in + c0h * r.th_in + c2t * r.t_out + c2h * r.th_out;
-    return dom == 0 ? u * r.cs - t * r.sn : u * r.sn + t * r.cs;
-}
 
 // Walk of one straight segment P0 -> P1 through the part of the grid whose
 // index along axis `ra` lies in [r_lo, r_hi] (Siddon's parametrisation
