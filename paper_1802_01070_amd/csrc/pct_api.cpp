@@ -33,7 +33,7 @@ Layout layout_for(int64_t nvox, int K, int dtype)
     L.table = off;
     off = align256(off + size_t(K + 1) * kRowDoubles * sizeof(double));
     L.acc = off;
-    off = align256(off + size_t(nvox) * vsize);
+    off = align256(off + size_t(nvox + 4) * vsize);  // +4: the commit reads words in groups of 4
     L.cnt = off;
     off = align256(off + size_t(nvox) * sizeof(int32_t));
     L.partial = off;
@@ -49,6 +49,7 @@ GridDev grid_dev(const pct_grid &g)
     for (int a = 0; a < 3; ++a) {
         d.n[a] = n[a];
         d.pitch[a] = g.pitch[a];
+        d.inv_pitch[a] = 1.0 / g.pitch[a];
         d.lo[a] = g.origin[a];
         d.hi[a] = g.origin[a] + n[a] * g.pitch[a];
     }

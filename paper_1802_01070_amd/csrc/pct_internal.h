@@ -18,6 +18,7 @@ constexpr int kMaxUploads = 16;
 struct GridDev {
     int32_t n[3];
     double pitch[3];
+    double inv_pitch[3];
     double lo[3];  // origin
     double hi[3];  // origin + n*pitch
 };

@@ -15,6 +15,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "pct_internal.h"
@@ -350,20 +351,25 @@ __device__ __forceinline__ bool group_any(bool p)
     return v != 0;
 }
 
-// Per-proton path state shared by the LPP lanes of its group, in LDS: the lab
-// coordinates of every vertex (P, 3 per vertex) and the signed coordinate of
-// every vertex along the dominant axis (A, increasing along the path).
+// Per-proton path state shared by the LPP lanes of its group.  The lab
+// coordinates of every vertex live in LDS (P, 3 doubles per vertex); the
+// signed coordinate along the dominant axis, A(k) = sgn * P[k][dom], increases
+// along a monotone path.
 struct GroupPath {
-    int dom;      // dominant in-plane axis (0: x, 1: y)
-    double sgn;   // direction of travel along it
+    int dom;         // dominant in-plane axis (0: x, 1: y)
+    double sgn;      // direction of travel along it
     int s_lo, s_hi;  // dominant-axis index range crossed by the path (s_lo > s_hi: none)
-    bool full;    // not monotone: lane 0 walks the whole row over the whole grid
+    bool full;       // not monotone: lane 0 walks the whole row over the whole grid
 };
+
+__device__ __forceinline__ double path_A(const GroupPath &gp, const double *__restrict__ P, int k)
+{
+    return gp.sgn * P[3 * k + gp.dom];
+}
 
 template <int LPP>
 __device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__restrict__ tab, int K,
-                                                const GridDev &g, double *__restrict__ P, double *__restrict__ A,
-                                                int l, bool active)
+                                                const GridDev &g, double *__restrict__ P, int l, bool active)
 {
     GroupPath gp;
     gp.dom = fabs(r.cs) >= fabs(r.sn) ? 0 : 1;
@@ -375,11 +381,10 @@ __device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__re
         P[3 * k] = v[0];
         P[3 * k + 1] = v[1];
         P[3 * k + 2] = v[2];
-        A[k] = gp.sgn * v[gp.dom];
     }
     __syncthreads();
     bool bad = !active;
-    for (int k = l; k < K; k += LPP) bad |= !(A[k + 1] > A[k]);
+    for (int k = l; k < K; k += LPP) bad |= !(path_A(gp, P, k + 1) > path_A(gp, P, k));
     gp.full = group_any<LPP>(bad);
     gp.s_lo = 0;
     gp.s_hi = -1;
@@ -388,9 +393,9 @@ __device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__re
         return gp;
     }
     const int a = gp.dom;
-    const double c0 = gp.sgn * A[0], c1 = gp.sgn * A[K];
-    const double f0 = floor((fmin(c0, c1) - g.lo[a]) / g.pitch[a]);
-    const double f1 = floor((fmax(c0, c1) - g.lo[a]) / g.pitch[a]);
+    const double c0 = P[a], c1 = P[3 * K + a];
+    const double f0 = floor((fmin(c0, c1) - g.lo[a]) * g.inv_pitch[a]);
+    const double f1 = floor((fmax(c0, c1) - g.lo[a]) * g.inv_pitch[a]);
     if (f1 < 0.0 || f0 > double(g.n[a] - 1)) return gp;
     gp.s_lo = int(fmax(f0, 0.0));
     gp.s_hi = int(fmin(f1, double(g.n[a] - 1)));
@@ -401,7 +406,7 @@ __device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__re
 // non-monotone path, every segment over the whole grid), feeding `m`.
 template <class M>
 __device__ __forceinline__ void walk_slab(const GroupPath &gp, int s, int K, const GridDev &g,
-                                          const double *__restrict__ P, const double *__restrict__ A, M &m)
+                                          const double *__restrict__ P, M &m)
 {
     const int a = gp.dom;
     if (gp.full) {
@@ -416,18 +421,18 @@ __device__ __forceinline__ void walk_slab(const GroupPath &gp, int s, int K, con
     const double lo_pl = g.lo[a] + s * g.pitch[a], hi_pl = g.lo[a] + (s + 1) * g.pitch[a];
     const double entry = gp.sgn > 0.0 ? lo_pl : -hi_pl;
     const double exitc = gp.sgn > 0.0 ? hi_pl : -lo_pl;
-    // last vertex k in [0, K-1] with A[k] <= entry
+    // last vertex k in [0, K-1] with A(k) <= entry
     int lo = 0, hi = K - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (A[mid] <= entry) lo = mid;
+        if (path_A(gp, P, mid) <= entry) lo = mid;
         else hi = mid - 1;
     }
     for (int k = lo; k < K; ++k) {
         const double *p0 = P + 3 * k, *p1 = P + 3 * k + 3;
         m.segment(p1[0] - p0[0], p1[1] - p0[1]);
         walk_segment_range(p0, p1, g, a, s, s, m);
-        if (A[k + 1] >= exitc) break;
+        if (path_A(gp, P, k + 1) >= exitc) break;
     }
 }
 
@@ -436,30 +441,66 @@ __device__ __forceinline__ void walk_slab(const GroupPath &gp, int s, int K, con
 // together along the path.
 template <int LPP, class M>
 __device__ __forceinline__ void walk_lane(const GroupPath &gp, int l, int K, const GridDev &g,
-                                          const double *__restrict__ P, const double *__restrict__ A, M &m)
+                                          const double *__restrict__ P, M &m)
 {
     if (gp.full) {
-        if (l == 0 && gp.s_hi >= gp.s_lo) walk_slab(gp, 0, K, g, P, A, m);
+        if (l == 0 && gp.s_hi >= gp.s_lo) walk_slab(gp, 0, K, g, P, m);
         return;
     }
     if (gp.sgn > 0.0) {
-        for (int s = gp.s_lo + l; s <= gp.s_hi; s += LPP) walk_slab(gp, s, K, g, P, A, m);
+        for (int s = gp.s_lo + l; s <= gp.s_hi; s += LPP) walk_slab(gp, s, K, g, P, m);
     } else {
-        for (int s = gp.s_hi - l; s >= gp.s_lo; s -= LPP) walk_slab(gp, s, K, g, P, A, m);
+        for (int s = gp.s_hi - l; s >= gp.s_lo; s -= LPP) walk_slab(gp, s, K, g, P, m);
     }
 }
 
-template <typename T, int CHORD, int LPP>
-__global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *__restrict__ b,
-                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
-                                                    const double *__restrict__ tab, int K, GridDev g, int64_t lo,
-                                                    int64_t hi, double lambda, unsigned *status)
+// Walk sink of the block kernel: tracks re-entries, accumulates ||a_i||^2 and
+// stashes the lane's merged pieces (voxel | first-visit bit, chord) in LDS,
+// entry-major so that the lanes of a wave hit different banks.
+template <typename CT, int S>
+struct StashSink {
+    int *__restrict__ sj;
+    CT *__restrict__ sc;
+    int lane;
+    Reentry re;
+    double n2;
+    int count;
+    __device__ __forceinline__ void segment(double dx, double dy) { re.segment(dx, dy); }
+    __device__ __forceinline__ void final(int j, int ix, int iy, int iz, double c)
+    {
+        bool first;
+        const double aprev = re.visit(j, ix, iy, iz, c, first);
+        n2 += c * (2.0 * aprev + c);
+        if (count < S) {
+            sj[count * 64 + lane] = first ? (j | int(0x80000000u)) : j;
+            sc[count * 64 + lane] = CT(c);
+        }
+        ++count;
+    }
+};
+
+constexpr int kStash = 16;  // pieces per lane kept in LDS; longer lanes walk again
+
+template <typename T>
+__host__ __device__ constexpr size_t stash_bytes()
 {
+    return size_t(64) * kStash * (sizeof(int) + (sizeof(T) == 4 ? sizeof(float) : sizeof(double)));
+}
+
+// Fused DROP block kernel: one wave per workgroup, 64 / LPP protons per wave.
+template <typename T, int CHORD, int LPP>
+__global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__restrict__ b,
+                                                   const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
+                                                   const double *__restrict__ tab, int K, GridDev g, int64_t lo,
+                                                   int64_t hi, double lambda, unsigned *status)
+{
+    using CT = typename std::conditional<sizeof(T) == 4, float, double>::type;
     extern __shared__ double lds[];
-    constexpr int GPB = kWG / LPP;  // proton groups per workgroup
-    const int grp = threadIdx.x / LPP;
-    const int l = threadIdx.x % LPP;
-    const int64_t i = lo + int64_t(blockIdx.x) * GPB + grp;
+    constexpr int GPW = 64 / LPP;  // proton groups per workgroup
+    const int lane = threadIdx.x;
+    const int grp = lane / LPP;
+    const int l = lane % LPP;
+    const int64_t i = lo + int64_t(blockIdx.x) * GPW + grp;
     bool active = i < hi;
     Rec r{};
     double bi = 0.0;
@@ -472,37 +513,79 @@ __global__ void __launch_bounds__(kWG) k_drop_block(ProtonsDev p, const float *_
         }
     }
     if (!active) r.cs = 1.0, r.sn = 0.0;
-    double *P = lds + grp * 4 * (K + 1);
-    double *A = P + 3 * (K + 1);
-    const GroupPath gp = stage_path<LPP>(r, tab, K, g, P, A, l, active);
+    double *P = lds + grp * 3 * (K + 1);
+    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * (K + 1));
+    int *sj = reinterpret_cast<int *>(stash);
+    CT *sc = reinterpret_cast<CT *>(stash + size_t(64) * kStash * sizeof(int));
+    const GroupPath gp = stage_path<LPP>(r, tab, K, g, P, l, active);
 
-    DotSink<T> s;
-    s.x = x;
-    s.dot = 0.0;
-    s.n2 = 0.0;
-    s.re.init(r);
+    // one walk: ||a_i||^2, re-entries and the stash of pieces
+    StashSink<CT, kStash> st{sj, sc, lane, {}, 0.0, 0};
+    st.re.init(r);
     {
-        Merge<DotSink<T>, CHORD> m(s, g);
-        walk_lane<LPP>(gp, l, K, g, P, A, m);
+        Merge<StashSink<CT, kStash>, CHORD> m(st, g);
+        walk_lane<LPP>(gp, l, K, g, P, m);
         m.finish();
     }
-    if (s.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
-    const double dot = group_sum<LPP>(s.dot);
-    const double n2 = group_sum<LPP>(s.n2);
-    DropScatterSink<T> sc;
-    sc.jmin = INT_MAX;
-    sc.jmax = -1;
+    if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
+    const bool spill = st.count > kStash;
+    const int ns = min(st.count, kStash);
+    // a_i . x: gathers from the stash (independent loads)
+    double dot = 0.0;
+    if (!spill) {
+#pragma unroll 4
+        for (int q = 0; q < ns; ++q) {
+            const int j = sj[q * 64 + lane] & 0x7FFFFFFF;
+            dot += double(sc[q * 64 + lane]) * double(x[j]);
+        }
+    } else {
+        DotSink<T> ds;
+        ds.x = x;
+        ds.dot = 0.0;
+        ds.n2 = 0.0;
+        ds.re.init(r);
+        Merge<DotSink<T>, CHORD> m(ds, g);
+        walk_lane<LPP>(gp, l, K, g, P, m);
+        m.finish();
+        dot = ds.dot;
+    }
+    dot = group_sum<LPP>(dot);
+    const double n2 = group_sum<LPP>(st.n2);
+    int jmin = INT_MAX, jmax = -1;
     if (n2 > 0.0) {
-        sc.acc = acc;
-        sc.cnt = cnt;
-        sc.status = status;
-        sc.rho = lambda * (bi - dot) / n2;
-        sc.re.init(r);
-        Merge<DropScatterSink<T>, CHORD> m(sc, g);
-        walk_lane<LPP>(gp, l, K, g, P, A, m);
-        m.finish();
+        const double rho = lambda * (bi - dot) / n2;
+        if (!spill) {
+            for (int q = 0; q < ns; ++q) {
+                const int e = sj[q * 64 + lane];
+                const int j = e & 0x7FFFFFFF;
+                const bool first = e < 0;
+                const double v = rho * double(sc[q * 64 + lane]);
+                if constexpr (sizeof(T) == 4) {
+                    atomicAdd(static_cast<unsigned long long *>(acc) + j, pack_contribution(v, first, status));
+                } else {
+                    atomicAdd(static_cast<double *>(acc) + j, v);
+                    if (first) atomicAdd(cnt + j, 1);
+                }
+                jmin = min(jmin, j);
+                jmax = max(jmax, j);
+            }
+        } else {
+            DropScatterSink<T> sc2;
+            sc2.acc = acc;
+            sc2.cnt = cnt;
+            sc2.status = status;
+            sc2.rho = rho;
+            sc2.jmin = INT_MAX;
+            sc2.jmax = -1;
+            sc2.re.init(r);
+            Merge<DropScatterSink<T>, CHORD> m(sc2, g);
+            walk_lane<LPP>(gp, l, K, g, P, m);
+            m.finish();
+            jmin = sc2.jmin;
+            jmax = sc2.jmax;
+        }
     }
-    publish_range(sc.jmin, sc.jmax, range);
+    publish_range(jmin, jmax, range);
 }
 
 // Commit of one block: a dense, coalesced scan of the block's touched index
@@ -519,18 +602,29 @@ __global__ void __launch_bounds__(kWG) k_drop_commit(T *x, void *accv, int32_t *
     }
     if (j1 < j0 || j0 < 0) return;  // nothing touched
     const int stride = int(gridDim.x * blockDim.x);
-    for (int j = j0 + int(blockIdx.x * blockDim.x + threadIdx.x); j <= j1; j += stride) {
-        if constexpr (sizeof(T) == 4) {
-            unsigned long long *pk = static_cast<unsigned long long *>(accv);
-            const unsigned long long w = pk[j];
-            if (w != 0ull) {
-                int c;
-                double sum;
-                unpack_accumulator(w, c, sum);
-                if (c > 0) x[j] = T(double(x[j]) + sum / double(c));
-                pk[j] = 0ull;
+    if constexpr (sizeof(T) == 4) {
+        // four 64-bit words per thread (the accumulator has 4 words of padding
+        // past the last voxel; untouched words are zero)
+        unsigned long long *pk = static_cast<unsigned long long *>(accv);
+        for (int j = (j0 & ~3) + 4 * int(blockIdx.x * blockDim.x + threadIdx.x); j <= j1; j += 4 * stride) {
+            const ulonglong2 w01 = *reinterpret_cast<const ulonglong2 *>(pk + j);
+            const ulonglong2 w23 = *reinterpret_cast<const ulonglong2 *>(pk + j + 2);
+            const unsigned long long w[4] = {w01.x, w01.y, w23.x, w23.y};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (w[e] != 0ull) {
+                    int c;
+                    double sum;
+                    unpack_accumulator(w[e], c, sum);
+                    if (c > 0) x[j + e] = T(double(x[j + e]) + sum / double(c));
+                    pk[j + e] = 0ull;
+                }
             }
-        } else {
+        }
+        return;
+    }
+    for (int j = j0 + int(blockIdx.x * blockDim.x + threadIdx.x); j <= j1; j += stride) {
+        {
             double *acc = static_cast<double *>(accv);
             const int c = cnt[j];
             if (c != 0) {
@@ -761,9 +855,9 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
     switch (lanes) {
 #define PCT_LAUNCH_LPP(LPP)                                                                                      \
     case LPP: {                                                                                                  \
-        const unsigned grid = unsigned((n + (kWG / LPP) - 1) / (kWG / LPP));                                  \
-        const size_t lds = size_t(kWG / LPP) * 4 * size_t(K + 1) * sizeof(double);                           \
-        hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP>), dim3(grid), dim3(kWG), lds, s, p, b, x, acc, cnt,      \
+        const unsigned grid = unsigned((n + (64 / LPP) - 1) / (64 / LPP));                                    \
+        const size_t lds = size_t(64 / LPP) * 3 * size_t(K + 1) * sizeof(double) + stash_bytes<T>();          \
+        hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP>), dim3(grid), dim3(64), lds, s, p, b, x, acc, cnt,       \
                            range, tab, K, g, lo, hi, lambda, status);                                             \
         break;                                                                                                   \
     }
@@ -788,7 +882,8 @@ static int choose_lanes(const pct_plan &pl, int requested)
         const int ndom = std::max(pl.grid.nx, pl.grid.ny);
         lanes = ndom >= 160 ? 64 : ndom >= 64 ? 32 : 16;
     }
-    if (lanes > 1 && size_t(kWG / lanes) * 4 * size_t(pl.K + 1) * sizeof(double) > kLdsBudget) lanes = 1;
+    if (lanes > 1 && size_t(64 / lanes) * 3 * size_t(pl.K + 1) * sizeof(double) + stash_bytes<double>() > kLdsBudget)
+        lanes = 1;
     return lanes;
 }
 

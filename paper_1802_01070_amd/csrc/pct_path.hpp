@@ -104,7 +104,7 @@ __device__ __forceinline__ void walk_segment_range(const double P0[3], const dou
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double pos = P0[a] + a_lo * d[a];
-        double q = (pos - g.lo[a]) / g.pitch[a];
+        double q = (pos - g.lo[a]) * g.inv_pitch[a];
         double f = floor(q);
         int i = int(fmin(fmax(f, -1.0), double(g.n[a])));
         if (d[a] < 0.0 && f == q) i -= 1;  // on a plane and moving down
