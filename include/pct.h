@@ -157,6 +157,12 @@ typedef struct {
 #define PCT_DROP_NO_GRAPH 0x2u     /* launch per block on the stream, no HIP graph   */
 #define PCT_DROP_PROFILE 0x4u      /* bracket a sample of the per-block kernels with
                                       HIP events on `stream` (see pct_profile_read) */
+/* FP32 value type with lanes > 1: by default the commit of block t-1 runs
+ * inside the launch of block t (block t reads x + D * block sum of t-1, the
+ * value the commit writes, so the result is bitwise that of the separate
+ * schedule).  This flag asks for the separate schedule: one block kernel and
+ * one commit kernel per block. */
+#define PCT_DROP_SEPARATE_COMMIT 0x8u
 
 /* Workspace bytes for problems of this plan (n protons, x of type dtype). */
 int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes);
@@ -196,17 +202,18 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
 
 /* Smoothed total variation (differentiation form): TV(x) = sum_v sqrt(dx^2 +
  * dy^2 + dz^2 + eps^2) with forward differences, zero at the last index of
- * every axis.  Writes the value to value_dev (device double[1]) and, if
- * grad != NULL, its gradient (float[nvox]).  x: float[nvox]. */
-int pct_tv(const pct_plan *plan, const float *x, double eps, double *value_dev, float *grad, void *ws,
-           size_t ws_bytes, void *stream);
+ * every axis.  Writes the value to value_dev (device double[1], summed in
+ * FP64) and, if grad != NULL, its gradient.  x, grad: dtype[nvox]. */
+int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
+           void *ws, size_t ws_bytes, void *stream);
 
 /* ---- diagnostics --------------------------------------------------------- */
 
 /* Kernel timing of the last pct_drop_iterate call made with PCT_DROP_PROFILE:
  * synchronises the recorded events and returns, per kernel kind (index 0: the
- * fused block kernel, 1: the block commit), the summed duration in ms of the
- * sampled launches and their number.  The plan keeps the events; profiling
+ * block kernel, with the commit of the previous block when that is fused into
+ * it; 1: the separate commit kernel, none when fused), the summed duration in
+ * ms of the sampled launches and their number.  The plan keeps the events; profiling
  * calls on one plan must not overlap. */
 int pct_profile_read(pct_plan *plan, double ms[2], int64_t launches[2]);
 const char *pct_status_string(int status);

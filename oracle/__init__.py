@@ -240,11 +240,10 @@ def tv_loss(grid, mlp, protons: dict, b: np.ndarray, x: np.ndarray, beta: float,
     return 0.5 * float(r @ r) + beta * tval, g
 
 
-def power_iteration(grid, mlp, protons: dict, n_steps: int = 20, seed: int = 0) -> float:
+def power_iteration(grid, mlp, protons: dict, v0: np.ndarray, n_steps: int = 20) -> float:
     """Estimate of the largest eigenvalue of A^T A by n_steps power steps from
-    a seeded positive start vector."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    v = rng.random(grid.nvox) + 0.5
+    the start vector v0 (an input: random draws are not the oracle's)."""
+    v = _f64(v0).copy()
     v /= np.linalg.norm(v)
     lam = 0.0
     for _ in range(n_steps):

@@ -18,6 +18,7 @@ CHORDS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 PCT_DROP_CHECK_FINITE = 0x1
 PCT_DROP_NO_GRAPH = 0x2
 PCT_DROP_PROFILE = 0x4
+PCT_DROP_SEPARATE_COMMIT = 0x8
 DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range"}
 FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out", "gantry")
 
@@ -75,7 +76,7 @@ def lib() -> C.CDLL:
             "pct_forward": ([vp, P(pct_protons), vp, i32, vp, vp, vp, sz, vp], C.c_int),
             "pct_backproject": ([vp, P(pct_protons), vp, i32, vp, vp, sz, vp], C.c_int),
             "pct_drop_iterate": ([vp, P(pct_protons), vp, vp, P(pct_drop_opts), vp, sz, vp], C.c_int),
-            "pct_tv": ([vp, vp, C.c_double, vp, vp, vp, sz, vp], C.c_int),
+            "pct_tv": ([vp, vp, i32, C.c_double, vp, vp, vp, sz, vp], C.c_int),
             "pct_status_string": ([C.c_int], C.c_char_p),
             "pct_last_hip_error": ([], C.c_int),
             "pct_profile_read": ([vp, P(C.c_double), P(i64)], C.c_int),

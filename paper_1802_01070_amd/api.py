@@ -159,10 +159,11 @@ def pct_drop_iterate(plan: Plan, p: Protons, b: torch.Tensor, x: torch.Tensor, b
 
 
 def pct_tv(plan: Plan, x: torch.Tensor, eps: float, with_grad: bool = True):
-    xp = _dev(x, "x", dtype=torch.float32, numel=plan.nvox)
+    code = _dtype_code(x)
+    xp = _dev(x, "x", numel=plan.nvox)
     val = torch.zeros(1, dtype=torch.float64, device=x.device)
     grad = torch.empty_like(x) if with_grad else None
-    st = lib().pct_tv(plan.handle, xp, float(eps), C.c_void_p(val.data_ptr()),
+    st = lib().pct_tv(plan.handle, xp, code, float(eps), C.c_void_p(val.data_ptr()),
                       C.c_void_p(grad.data_ptr()) if with_grad else None, plan.ws_ptr, plan.ws_bytes,
                       _stream(x.device))
     check(st, "pct_tv")
@@ -229,3 +230,47 @@ class DropSolver:
 
     def run(self, x: torch.Tensor, block: int, lam: float, n_iter: int, chord: str = "f64", **kw):
         return pct_drop_iterate(self.plan, self.p, self.b, x, block, lam, n_iter, chord=chord, **kw)
+
+
+def tv_objective(plan: Plan, protons: Protons, b: torch.Tensor, x: torch.Tensor, beta: float, eps: float):
+    """L(x) = 1/2 ||A x - b||^2 + beta TV_eps(x) as a torch graph over ProjectFn
+    and TVFn (the residual norm is reduced in FP64)."""
+    y = ProjectFn.apply(x, plan, protons)
+    r = y.double() - b.double()
+    return 0.5 * (r * r).sum() + beta * TVFn.apply(x, plan, eps).double()
+
+
+def power_iteration(plan: Plan, protons: Protons, v0: torch.Tensor, n_steps: int = 20) -> float:
+    """Largest eigenvalue of A^T A by n_steps power steps from the start vector
+    v0 (forward and back projection kernels, in v0's dtype)."""
+    dtype = v0.dtype
+    v = v0.detach().clone()
+    v /= torch.linalg.vector_norm(v)
+    lam = 0.0
+    for _ in range(n_steps):
+        y = pct_forward(plan, protons, v)
+        w = pct_backproject(plan, protons, y)
+        lam = float(torch.linalg.vector_norm(w.double()))
+        v = (w / lam).to(dtype)
+    return lam
+
+
+def tv_gradient_descent(plan: Plan, protons: Protons, b: torch.Tensor, x0: torch.Tensor, beta: float,
+                        eps: float, n_steps: int, eta: Optional[float] = None, v0: Optional[torch.Tensor] = None,
+                        power_steps: int = 20):
+    """Fixed-step gradient descent on the TV-regularised least-squares
+    objective; eta defaults to 1 / (lambda_max(A^T A) + 12 beta / eps) with the
+    eigenvalue from power iteration started at v0.  Returns (x, losses, eta)."""
+    if eta is None:
+        if v0 is None:
+            raise ValueError("eta or a power-iteration start vector v0 is required")
+        eta = 1.0 / (power_iteration(plan, protons, v0, power_steps) + 12.0 * beta / eps)
+    x = x0.detach().clone()
+    losses = []
+    for _ in range(n_steps):
+        x.requires_grad_(True)
+        loss = tv_objective(plan, protons, b, x, beta, eps)
+        (g,) = torch.autograd.grad(loss, x)
+        losses.append(float(loss))
+        x = (x.detach() - eta * g).detach()
+    return x, losses, eta

@@ -33,9 +33,12 @@ Layout layout_for(int64_t nvox, int K, int dtype)
     L.table = off;
     off = align256(off + size_t(K + 1) * kRowDoubles * sizeof(double));
     L.acc = off;
-    off = align256(off + size_t(nvox + 4) * vsize);  // +4: the commit reads words in groups of 4
+    L.acc_stride = align256(size_t(nvox + 4) * vsize);  // +4: the commit reads words in groups of 4
+    off = align256(off + 3 * L.acc_stride);
     L.cnt = off;
     off = align256(off + size_t(nvox) * sizeof(int32_t));
+    L.x1 = off;
+    off = align256(off + size_t(nvox) * sizeof(double));
     L.partial = off;
     off = align256(off + size_t(kMaxPartials) * sizeof(double));
     L.total = off;
@@ -346,7 +349,8 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (p->n > 0 && !b) return PCT_ERR_INVALID_ARG;
     if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
     if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
-    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE)) return PCT_ERR_INVALID_ARG;
+    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT))
+        return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
     if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 20)) return PCT_ERR_INVALID_ARG;
     if (o->lanes != 0 && o->lanes != 1 && o->lanes != 8 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64)
@@ -363,13 +367,13 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     return hip_status(launch_drop(*const_cast<pct_plan *>(plan), protons_dev(p), p->n, b, x, oo, ws, stream));
 }
 
-int pct_tv(const pct_plan *plan, const float *x, double eps, double *value_dev, float *grad, void *ws,
-           size_t ws_bytes, void *stream)
+int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
+           void *ws, size_t ws_bytes, void *stream)
 {
-    if (!plan || !x || !value_dev || !finite_pos(eps)) return PCT_ERR_INVALID_ARG;
-    int st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (!plan || !x || !value_dev || !finite_pos(eps) || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
+    int st = check_ws(plan, ws, ws_bytes, dtype);
     if (st) return st;
-    return hip_status(launch_tv(*plan, x, eps, value_dev, grad, ws, stream));
+    return hip_status(launch_tv(*plan, x, dtype, eps, value_dev, grad, ws, stream));
 }
 
 const char *pct_status_string(int status)

@@ -31,16 +31,19 @@ struct ProtonsDev {
 struct Layout {
     size_t hdr;      // status word and counters (256 B)
     size_t table;    // (K+1) * kRowDoubles doubles
-    size_t acc;      // nvox * sizeof(dtype)
+    size_t acc;      // three block accumulators of (nvox + 4) 64-bit words
+    size_t acc_stride;  // bytes between consecutive accumulators
     size_t cnt;      // nvox int32
+    size_t x1;       // second copy of the iterate, nvox doubles
     size_t partial;  // kMaxPartials doubles
     size_t total;
 };
 constexpr int kMaxPartials = 4096;
 
 // header words (int32 index): status word, then the [jmin, jmax] voxel range
-// touched by a block, double-buffered by block parity
-enum : int { kHdrStatus = 0, kHdrRange0 = 2, kHdrRange1 = 4 };
+// touched by a block, double-buffered by block parity (FP64 path), and four
+// rotating range slots of the fused FP32 path
+enum : int { kHdrStatus = 0, kHdrRange0 = 2, kHdrRange1 = 4, kHdrSlots = 8 };
 
 Layout layout_for(int64_t nvox, int K, int dtype);
 
@@ -75,7 +78,7 @@ int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const
                        void *ws, void *stream);
 int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x,
                 const pct_drop_opts &o, void *ws, void *stream);
-int launch_tv(const pct_plan &pl, const float *x, double eps, double *value_dev, float *grad, void *ws,
+int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,
               void *stream);
 int upload_table(const pct_plan &pl, void *ws, void *stream);
 int profile_read(pct_plan &pl, double ms[2], int64_t launches[2]);

@@ -108,9 +108,16 @@ __global__ void __launch_bounds__(kWG) k_trace(ProtonsDev p, int64_t first, int6
 // ---------------------------------------------------------------------------
 // forward projection
 // ---------------------------------------------------------------------------
+// Value of the iterate at voxel j seen by a block.
 template <typename T>
-struct DotSink {
+struct PlainX {
     const T *__restrict__ x;
+    __device__ __forceinline__ double operator()(int j) const { return double(x[j]); }
+};
+
+template <typename T, class XA = PlainX<T>>
+struct DotSink {
+    XA x;
     Reentry re;
     double dot, n2;
     __device__ __forceinline__ void segment(double dx, double dy) { re.segment(dx, dy); }
@@ -118,7 +125,7 @@ struct DotSink {
     {
         bool first;
         double aprev = re.visit(j, ix, iy, iz, c, first);
-        dot += c * double(x[j]);
+        dot += c * x(j);
         n2 += c * (2.0 * aprev + c);
     }
 };
@@ -131,7 +138,7 @@ __global__ void __launch_bounds__(kWG) k_forward(ProtonsDev p, int64_t n, const 
     if (i >= n) return;
     Rec r = load_rec(p, i);
     DotSink<T> s;
-    s.x = x;
+    s.x = PlainX<T>{x};
     s.dot = 0.0;
     s.n2 = 0.0;
     s.re.init(r);
@@ -294,7 +301,7 @@ __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__
     sc.jmax = -1;
     if (active) {
         DotSink<T> s;
-        s.x = x;
+        s.x = PlainX<T>{x};
         s.dot = 0.0;
         s.n2 = 0.0;
         s.re.init(r);
@@ -402,14 +409,17 @@ __device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__re
     return gp;
 }
 
-// Walks the pieces of the path inside dominant-axis slab `s` (or, for a
-// non-monotone path, every segment over the whole grid), feeding `m`.
-template <class M>
-__device__ __forceinline__ void walk_slab(const GroupPath &gp, int s, int K, const GridDev &g,
+// The lane's share of the path: a contiguous range of dominant-axis slabs
+// (lanes take consecutive ranges in the direction of travel), walked as one
+// run of segments clipped to the range.  A non-monotone path is walked whole
+// by lane 0.
+template <int LPP, class M>
+__device__ __forceinline__ void walk_lane(const GroupPath &gp, int l, int K, const GridDev &g,
                                           const double *__restrict__ P, M &m)
 {
     const int a = gp.dom;
     if (gp.full) {
+        if (l != 0 || gp.s_hi < gp.s_lo) return;
         for (int k = 0; k < K; ++k) {
             const double *p0 = P + 3 * k, *p1 = P + 3 * k + 3;
             m.segment(p1[0] - p0[0], p1[1] - p0[1]);
@@ -417,10 +427,23 @@ __device__ __forceinline__ void walk_slab(const GroupPath &gp, int s, int K, con
         }
         return;
     }
-    // entry and exit planes of the slab in signed coordinate
-    const double lo_pl = g.lo[a] + s * g.pitch[a], hi_pl = g.lo[a] + (s + 1) * g.pitch[a];
-    const double entry = gp.sgn > 0.0 ? lo_pl : -hi_pl;
-    const double exitc = gp.sgn > 0.0 ? hi_pl : -lo_pl;
+    const int ns = gp.s_hi - gp.s_lo + 1;
+    if (ns <= 0) return;
+    const int q = ns / LPP, rem = ns % LPP;
+    const int off = l * q + min(l, rem);
+    const int cntl = q + (l < rem ? 1 : 0);
+    if (cntl <= 0) return;
+    int s0, s1;
+    if (gp.sgn > 0.0) {
+        s0 = gp.s_lo + off;
+        s1 = s0 + cntl - 1;
+    } else {
+        s1 = gp.s_hi - off;
+        s0 = s1 - cntl + 1;
+    }
+    // entry and exit planes of the range in signed coordinate
+    const double entry = gp.sgn > 0.0 ? g.lo[a] + s0 * g.pitch[a] : -(g.lo[a] + (s1 + 1) * g.pitch[a]);
+    const double exitc = gp.sgn > 0.0 ? g.lo[a] + (s1 + 1) * g.pitch[a] : -(g.lo[a] + s0 * g.pitch[a]);
     // last vertex k in [0, K-1] with A(k) <= entry
     int lo = 0, hi = K - 1;
     while (lo < hi) {
@@ -430,27 +453,8 @@ __device__ __forceinline__ void walk_slab(const GroupPath &gp, int s, int K, con
     }
     for (int k = lo; k < K; ++k) {
         const double *p0 = P + 3 * k, *p1 = P + 3 * k + 3;
-        m.segment(p1[0] - p0[0], p1[1] - p0[1]);
-        walk_segment_range(p0, p1, g, a, s, s, m);
+        walk_segment_range(p0, p1, g, a, s0, s1, m);
         if (path_A(gp, P, k + 1) >= exitc) break;
-    }
-}
-
-// The slabs of a lane: s_lo + l, s_lo + l + LPP, ...  Interleaving the lanes
-// over consecutive slabs keeps the voxels a wave touches at one step close
-// together along the path.
-template <int LPP, class M>
-__device__ __forceinline__ void walk_lane(const GroupPath &gp, int l, int K, const GridDev &g,
-                                          const double *__restrict__ P, M &m)
-{
-    if (gp.full) {
-        if (l == 0 && gp.s_hi >= gp.s_lo) walk_slab(gp, 0, K, g, P, m);
-        return;
-    }
-    if (gp.sgn > 0.0) {
-        for (int s = gp.s_lo + l; s <= gp.s_hi; s += LPP) walk_slab(gp, s, K, g, P, m);
-    } else {
-        for (int s = gp.s_hi - l; s >= gp.s_lo; s -= LPP) walk_slab(gp, s, K, g, P, m);
     }
 }
 
@@ -479,7 +483,7 @@ struct StashSink {
     }
 };
 
-constexpr int kStash = 16;  // pieces per lane kept in LDS; longer lanes walk again
+constexpr int kStash = 12;  // pieces per lane kept in LDS; longer lanes walk again
 
 template <typename T>
 __host__ __device__ constexpr size_t stash_bytes()
@@ -540,7 +544,7 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
         }
     } else {
         DotSink<T> ds;
-        ds.x = x;
+        ds.x = PlainX<T>{x};
         ds.dot = 0.0;
         ds.n2 = 0.0;
         ds.re.init(r);
@@ -586,6 +590,195 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
         }
     }
     publish_range(jmin, jmax, range);
+}
+
+// ---------------------------------------------------------------------------
+// Fused FP32 DROP sweep: the commit of block q-1 happens inside the launch of
+// block q.
+//
+// Two copies of the iterate (X0 = the caller's x, X1 in the workspace) and
+// three packed accumulators rotate with the block index q of the sweep:
+//   base = X[q % 2] holds every block before q-1;  PK[(q-1) % 3] holds block
+//   q-1's sums.  Block q reads  xbar_j = base_j + sum_j / s_j  (the committed
+//   value of block q-1, computed on the fly) and scatters into PK[q % 3].
+//   In the same launch, commit workgroups write X[(q+1) % 2] = base + update
+//   over the index ranges of blocks q-1 and q-2 (the only places where the two
+//   copies differ) and clear PK[(q-2) % 3].  Nothing read in a launch is
+//   written in it, so no grid-wide synchronisation is needed, and the commit's
+//   memory traffic overlaps the walk.  A flush kernel ends the sweep.
+// Range slots rotate over 4: block q accumulates slot q%4, reads q-1 and q-2,
+// and re-arms slot (q+1)%4 for the next block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float committed_value(float base, unsigned long long w)
+{
+    if (w == 0ull) return base;
+    int c;
+    double sum;
+    unpack_accumulator(w, c, sum);
+    return float(double(base) + sum / double(c));
+}
+
+struct LazyX {
+    const float *__restrict__ base;
+    const unsigned long long *__restrict__ pk;
+    __device__ __forceinline__ double operator()(int j) const { return double(committed_value(base[j], pk[j])); }
+};
+
+__device__ __forceinline__ void commit_part(const float *__restrict__ base, float *__restrict__ next,
+                                            const unsigned long long *__restrict__ pk_prev,
+                                            unsigned long long *__restrict__ pk_old, const int *r_prev,
+                                            const int *r_old, int *r_reset, int nvox, int wg, int n_wg)
+{
+    const int j0 = min(r_prev[0], r_old[0]);
+    const int j1 = max(r_prev[1], r_old[1]);
+    if (wg == 0 && threadIdx.x == 0) {
+        r_reset[0] = INT_MAX;
+        r_reset[1] = -1;
+    }
+    if (j1 < j0 || j0 < 0) return;
+    const int stride = 4 * n_wg * int(blockDim.x);
+    for (int j = (j0 & ~3) + 4 * (wg * int(blockDim.x) + int(threadIdx.x)); j <= j1; j += stride) {
+        const ulonglong2 p01 = *reinterpret_cast<const ulonglong2 *>(pk_prev + j);
+        const ulonglong2 p23 = *reinterpret_cast<const ulonglong2 *>(pk_prev + j + 2);
+        const ulonglong2 o01 = *reinterpret_cast<const ulonglong2 *>(pk_old + j);
+        const ulonglong2 o23 = *reinterpret_cast<const ulonglong2 *>(pk_old + j + 2);
+        const unsigned long long wp[4] = {p01.x, p01.y, p23.x, p23.y};
+        const unsigned long long wo[4] = {o01.x, o01.y, o23.x, o23.y};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int jj = j + e;
+            if (jj < nvox) next[jj] = committed_value(base[jj], wp[e]);
+            if (wo[e] != 0ull) pk_old[jj] = 0ull;
+        }
+    }
+}
+
+constexpr int kCommitWG = 1024;  // commit workgroups (64 threads) per fused launch
+
+template <int CHORD, int LPP>
+__global__ void __launch_bounds__(64) k_drop_fused(ProtonsDev p, const float *__restrict__ b,
+                                                   const float *__restrict__ base, float *__restrict__ next,
+                                                   const unsigned long long *__restrict__ pk_prev,
+                                                   unsigned long long *pk_cur, unsigned long long *pk_old, int *r_cur,
+                                                   const int *r_prev, const int *r_old, int *r_reset,
+                                                   const double *__restrict__ tab, int K, GridDev g, int64_t lo,
+                                                   int64_t hi, double lambda, unsigned *status, int nvox)
+{
+    if (int(blockIdx.x) < kCommitWG) {
+        commit_part(base, next, pk_prev, pk_old, r_prev, r_old, r_reset, nvox, int(blockIdx.x), kCommitWG);
+        return;
+    }
+    using CT = float;
+    extern __shared__ double lds[];
+    constexpr int GPW = 64 / LPP;
+    const int lane = threadIdx.x;
+    const int grp = lane / LPP;
+    const int l = lane % LPP;
+    const int64_t i = lo + int64_t(blockIdx.x - kCommitWG) * GPW + grp;
+    bool active = i < hi;
+    Rec r{};
+    double bi = 0.0;
+    if (active) {
+        r = load_rec(p, i);
+        bi = double(b[i]);
+        if (!rec_finite(r) || !isfinite(bi)) {
+            if (l == 0) raise_status(status, PCT_DEV_NONFINITE);
+            active = false;
+        }
+    }
+    if (!active) r.cs = 1.0, r.sn = 0.0;
+    double *P = lds + grp * 3 * (K + 1);
+    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * (K + 1));
+    int *sj = reinterpret_cast<int *>(stash);
+    CT *sc = reinterpret_cast<CT *>(stash + size_t(64) * kStash * sizeof(int));
+    const GroupPath gp = stage_path<LPP>(r, tab, K, g, P, l, active);
+
+    StashSink<CT, kStash> st{sj, sc, lane, {}, 0.0, 0};
+    st.re.init(r);
+    {
+        Merge<StashSink<CT, kStash>, CHORD> m(st, g);
+        walk_lane<LPP>(gp, l, K, g, P, m);
+        m.finish();
+    }
+    if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
+    const bool spill = st.count > kStash;
+    const int ns = min(st.count, kStash);
+    const LazyX xa{base, pk_prev};
+    double dot = 0.0;
+    if (!spill) {
+#pragma unroll 4
+        for (int q = 0; q < ns; ++q) {
+            const int j = sj[q * 64 + lane] & 0x7FFFFFFF;
+            dot += double(sc[q * 64 + lane]) * xa(j);
+        }
+    } else {
+        DotSink<float, LazyX> ds;
+        ds.x = xa;
+        ds.dot = 0.0;
+        ds.n2 = 0.0;
+        ds.re.init(r);
+        Merge<DotSink<float, LazyX>, CHORD> m(ds, g);
+        walk_lane<LPP>(gp, l, K, g, P, m);
+        m.finish();
+        dot = ds.dot;
+    }
+    dot = group_sum<LPP>(dot);
+    const double n2 = group_sum<LPP>(st.n2);
+    int jmin = INT_MAX, jmax = -1;
+    if (n2 > 0.0) {
+        const double rho = lambda * (bi - dot) / n2;
+        if (!spill) {
+            for (int q = 0; q < ns; ++q) {
+                const int e = sj[q * 64 + lane];
+                const int j = e & 0x7FFFFFFF;
+                atomicAdd(pk_cur + j, pack_contribution(rho * double(sc[q * 64 + lane]), e < 0, status));
+                jmin = min(jmin, j);
+                jmax = max(jmax, j);
+            }
+        } else {
+            DropScatterSink<float> sc2;
+            sc2.acc = pk_cur;
+            sc2.cnt = nullptr;
+            sc2.status = status;
+            sc2.rho = rho;
+            sc2.jmin = INT_MAX;
+            sc2.jmax = -1;
+            sc2.re.init(r);
+            Merge<DropScatterSink<float>, CHORD> m(sc2, g);
+            walk_lane<LPP>(gp, l, K, g, P, m);
+            m.finish();
+            jmin = sc2.jmin;
+            jmax = sc2.jmax;
+        }
+    }
+    publish_range(jmin, jmax, r_cur);
+}
+
+// Start of a fused sweep: X1 = x, all range slots empty.
+__global__ void __launch_bounds__(256) k_sweep_begin(const float *__restrict__ x, float *__restrict__ x1, int *slots,
+                                                     int nvox)
+{
+    const int t = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t < 8 && blockIdx.x == 0) slots[t] = (t & 1) ? -1 : INT_MAX;
+    for (int j = t; j < nvox; j += int(gridDim.x * blockDim.x)) x1[j] = x[j];
+}
+
+// End of a fused sweep of T blocks: x = X[T%2] + update of block T-1 over the
+// ranges of blocks T-1 and T-2; clears the accumulators of both.
+__global__ void __launch_bounds__(256) k_sweep_end(float *x, const float *src, unsigned long long *pk_last,
+                                                   unsigned long long *pk_prev, const int *r_last, const int *r_prev,
+                                                   int nvox)
+{
+    const int j0 = min(r_last[0], r_prev[0]);
+    const int j1 = max(r_last[1], r_prev[1]);
+    if (j1 < j0 || j0 < 0) return;
+    for (int j = j0 + int(blockIdx.x * blockDim.x + threadIdx.x); j <= j1 && j < nvox;
+         j += int(gridDim.x * blockDim.x)) {
+        const unsigned long long w = pk_last[j];
+        x[j] = committed_value(src[j], w);
+        if (w != 0ull) pk_last[j] = 0ull;
+        if (pk_prev[j] != 0ull) pk_prev[j] = 0ull;
+    }
 }
 
 // Commit of one block: a dense, coalesced scan of the block's touched index
@@ -649,7 +842,8 @@ __global__ void k_reset_ranges(int *hdr)
 // ---------------------------------------------------------------------------
 // total variation
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double tv_diffs(const float *__restrict__ x, const GridDev &g, int ix, int iy, int iz,
+template <typename T>
+__device__ __forceinline__ double tv_diffs(const T *__restrict__ x, const GridDev &g, int ix, int iy, int iz,
                                            int64_t v, double eps, double &dx, double &dy, double &dz)
 {
     const int64_t sy = g.n[0], sz = int64_t(g.n[0]) * g.n[1];
@@ -660,7 +854,8 @@ __device__ __forceinline__ double tv_diffs(const float *__restrict__ x, const Gr
     return sqrt(dx * dx + dy * dy + dz * dz + eps * eps);
 }
 
-__global__ void __launch_bounds__(kWG) k_tv(const float *__restrict__ x, GridDev g, double eps, float *grad,
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_tv(const T *__restrict__ x, GridDev g, double eps, T *grad,
                                             double *partial, int64_t nvox)
 {
     __shared__ double red[kWG];
@@ -679,7 +874,7 @@ __global__ void __launch_bounds__(kWG) k_tv(const float *__restrict__ x, GridDev
             if (ix > 0) gv += (double(x[v]) - double(x[v - 1])) / tv_diffs(x, g, ix - 1, iy, iz, v - 1, eps, ex, ey, ez);
             if (iy > 0) gv += (double(x[v]) - double(x[v - sy])) / tv_diffs(x, g, ix, iy - 1, iz, v - sy, eps, ex, ey, ez);
             if (iz > 0) gv += (double(x[v]) - double(x[v - sz])) / tv_diffs(x, g, ix, iy, iz - 1, v - sz, eps, ex, ey, ez);
-            grad[v] = float(gv);
+            grad[v] = T(gv);
         }
     }
     red[threadIdx.x] = local;
@@ -872,6 +1067,35 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
     }
 }
 
+// Launch q of a fused FP32 sweep (see k_drop_fused): commit workgroups first,
+// then the proton workgroups of block [lo, hi).
+template <int CHORD>
+static void launch_fused(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, const float *base,
+                         float *next, const unsigned long long *pk_prev, unsigned long long *pk_cur,
+                         unsigned long long *pk_old, int *r_cur, const int *r_prev, const int *r_old, int *r_reset,
+                         const double *tab, int K, const GridDev &g, int64_t lo, int64_t hi, double lambda,
+                         unsigned *status, int nvox)
+{
+    const int64_t n = hi - lo;
+    switch (lanes) {
+#define PCT_LAUNCH_FUSED(LPP)                                                                                    \
+    case LPP: {                                                                                                  \
+        const unsigned grid = unsigned(kCommitWG + (n + (64 / LPP) - 1) / (64 / LPP));                        \
+        const size_t lds = size_t(64 / LPP) * 3 * size_t(K + 1) * sizeof(double) + stash_bytes<float>();      \
+        hipLaunchKernelGGL((k_drop_fused<CHORD, LPP>), dim3(grid), dim3(64), lds, s, p, b, base, next, pk_prev,  \
+                           pk_cur, pk_old, r_cur, r_prev, r_old, r_reset, tab, K, g, lo, hi, lambda, status,     \
+                           nvox);                                                                                \
+        break;                                                                                                   \
+    }
+        PCT_LAUNCH_FUSED(8)
+        PCT_LAUNCH_FUSED(16)
+        PCT_LAUNCH_FUSED(32)
+        PCT_LAUNCH_FUSED(64)
+#undef PCT_LAUNCH_FUSED
+    default: break;
+    }
+}
+
 // Lanes per proton: enough lanes that each walks a few slabs of the dominant
 // axis, within the LDS budget of the staged vertex coordinates.
 static int choose_lanes(const pct_plan &pl, int requested)
@@ -943,9 +1167,55 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         }
     };
 
+    // Fused FP32 sweep: X[0] = x, X[1] in the workspace, accumulators PK[0..2],
+    // range slots R[0..3] (header words from kHdrSlots), all indexed by the
+    // block's position q in the sweep.
+    auto enqueue_fused_sweep = [&](hipStream_t s, bool record_events) {
+        if constexpr (sizeof(T) == 4) {
+            float *X[2] = {x, reinterpret_cast<float *>(wsb(ws) + L.x1)};
+            unsigned long long *PK[3];
+            for (int k = 0; k < 3; ++k)
+                PK[k] = reinterpret_cast<unsigned long long *>(wsb(ws) + L.acc + size_t(k) * L.acc_stride);
+            int *R[4];
+            for (int k = 0; k < 4; ++k) R[k] = hdr + kHdrSlots + 2 * k;
+            const int nv = int(pl.nvox);
+            const unsigned copy_grid = unsigned(std::min<int64_t>(2048, (pl.nvox + 255) / 256));
+            hipLaunchKernelGGL(k_sweep_begin, dim3(copy_grid), dim3(256), 0, s, X[0], X[1], R[0], nv);
+            int64_t q = 0;
+            for (int64_t t = o.block_begin; t < o.block_end; ++t, ++q) {
+                const int64_t lo = t * o.block;
+                const int64_t hi = std::min<int64_t>(n, lo + o.block);
+                const bool sample = record_events && (q % every == 0) && pl.prof_used[0] < kProfSamples;
+                if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
+                launch_fused<CHORD>(lanes, s, p, b, X[q % 2], X[(q + 1) % 2], PK[(q + 2) % 3], PK[q % 3],
+                                    PK[(q + 1) % 3], R[q % 4], R[(q + 3) % 4], R[(q + 2) % 4], R[(q + 1) % 4], tab,
+                                    pl.K, g, lo, hi, o.lambda, status, nv);
+                if (sample) {
+                    (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
+                    pl.prof_used[0]++;
+                }
+            }
+            if (q > 0) {
+                const int64_t last = q - 1;
+                hipLaunchKernelGGL(k_sweep_end, dim3(copy_grid), dim3(256), 0, s, X[0], X[q % 2], PK[last % 3],
+                                   PK[(last + 2) % 3], R[last % 4], R[(last + 3) % 4], nv);
+            }
+        } else {
+            (void)s;
+            (void)record_events;
+        }
+    };
+    const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT);
+    auto sweep = [&](hipStream_t s, bool record_events) {
+        if (fused)
+            enqueue_fused_sweep(s, record_events);
+        else
+            enqueue_sweep(s, record_events);
+    };
+
     const bool use_graph = !(o.flags & PCT_DROP_NO_GRAPH) && !prof;
     if (!use_graph) {
-        for (int it = 0; it < o.n_iter; ++it) enqueue_sweep(s, prof && it == o.n_iter - 1);
+        for (int it = 0; it < o.n_iter; ++it) sweep(s, prof && it == o.n_iter - 1);
         return hipGetLastError();
     }
     // The sweep is captured once into a HIP graph and replayed; the graph is
@@ -958,7 +1228,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         reinterpret_cast<uint64_t>(p.gantry), reinterpret_cast<uint64_t>(b),
         reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
         uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
-        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), 0};
+        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), uint64_t(fused), 0};
     std::memcpy(&key.back(), &o.lambda, sizeof(double));
     if (!pl.graph_exec || pl.graph_key != key) {
         // recorded on a private stream (the caller's stream may be the null
@@ -975,7 +1245,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         hipStream_t cs = static_cast<hipStream_t>(pl.capture_stream);
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        enqueue_sweep(cs, false);
+        sweep(cs, false);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
         if (e != hipSuccess) return e;
@@ -1013,14 +1283,19 @@ int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, vo
     return drop_dispatch_chord<float>(pl, p, n, b, static_cast<float *>(x), o, ws, s);
 }
 
-int launch_tv(const pct_plan &pl, const float *x, double eps, double *value_dev, float *grad, void *ws,
+int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,
               void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    Layout L = layout_for(pl.nvox, pl.K, dtype);
     double *partial = reinterpret_cast<double *>(wsb(ws) + L.partial);
     int nblk = int(std::min<int64_t>(kMaxPartials, (pl.nvox + kWG - 1) / kWG));
-    hipLaunchKernelGGL(k_tv, dim3(nblk), dim3(kWG), 0, s, x, grid_dev(pl.grid), eps, grad, partial, pl.nvox);
+    if (dtype == PCT_F64)
+        hipLaunchKernelGGL(k_tv<double>, dim3(nblk), dim3(kWG), 0, s, static_cast<const double *>(x),
+                           grid_dev(pl.grid), eps, static_cast<double *>(grad), partial, pl.nvox);
+    else
+        hipLaunchKernelGGL(k_tv<float>, dim3(nblk), dim3(kWG), 0, s, static_cast<const float *>(x),
+                           grid_dev(pl.grid), eps, static_cast<float *>(grad), partial, pl.nvox);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, partial, nblk, value_dev);
     return hipGetLastError();
 }

@@ -388,6 +388,12 @@ def make_scan(cfg: ScanConfig, m: Optional[int] = None, seed: Optional[int] = No
     return Scan(cfg.with_(m=m, seed=seed), grid, mlp, out, b, phantom)
 
 
+def power_start(nvox: int, seed: int = 0) -> np.ndarray:
+    """Seeded positive start vector for power iteration (uniform in [0.5, 1.5))."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
+    return rng.random(nvox) + 0.5
+
+
 def make_rays(grid: Grid, mlp: MLPModel, rays: Sequence[Sequence[float]]) -> dict:
     """Hand-placed protons: each ray is (t_in, v_in, th_in, ph_in, t_out, v_out,
     th_out, ph_out, gantry)."""

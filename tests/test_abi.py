@@ -156,7 +156,7 @@ def test_compute_calls_validate_before_device(plan):
 
 
 @pytest.mark.parametrize("field,value", [("block", 0), ("lambda_", 0.0), ("lambda_", float("inf")), ("n_iter", -1),
-                                         ("dtype", 3), ("chord", 9), ("flags", 0x80), ("block_begin", -1),
+                                         ("dtype", 3), ("chord", 9), ("flags", 0x10), ("block_begin", -1),
                                          ("block_end", 2), ("block_begin", 3), ("lanes", 2), ("lanes", 128),
                                          ("reserved", 1)])
 def test_drop_options_validated(plan, field, value):
@@ -185,9 +185,10 @@ def test_drop_valid_options_reach_workspace_check(plan):
 def test_tv_validation(plan):
     L = _lib.lib()
     nb = ws_size(plan)
-    assert L.pct_tv(plan, None, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
-    assert L.pct_tv(plan, C.c_void_p(8), 0.0, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
-    assert L.pct_tv(plan, C.c_void_p(8), 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -2
+    assert L.pct_tv(plan, None, 0, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
+    assert L.pct_tv(plan, C.c_void_p(8), 0, 0.0, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
+    assert L.pct_tv(plan, C.c_void_p(8), 3, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
+    assert L.pct_tv(plan, C.c_void_p(8), 0, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -2
 
 
 def test_status_strings():

@@ -467,3 +467,90 @@ def test_fp32_drop_is_bitwise_reproducible():
     for r in runs[1:]:
         assert torch.equal(runs[0], r)
     assert_status_clean(plan)
+
+
+def test_fused_commit_is_bitwise_the_separate_schedule():
+    # FP32 with lanes > 1 folds the commit of block t-1 into the launch of
+    # block t; the arithmetic is the same, so the result must be bitwise that
+    # of one block kernel + one commit kernel per block, for any number of
+    # blocks (odd and even, to exercise the ping-pong and rotations), any
+    # starting block, graph or per-block launches, and repeated sweeps
+    from paper_1802_01070_amd._lib import PCT_DROP_NO_GRAPH, PCT_DROP_SEPARATE_COMMIT
+    c = synth.CONFIGS[2]
+    sc = scan(2, 64000)
+    plan, pr = gpu_setup(sc)
+    b = torch.from_numpy(sc.b).to(DEV)
+    x0 = torch.from_numpy(np.random.default_rng(9).uniform(0.9, 1.1, sc.grid.nvox).astype(np.float32)).to(DEV)
+    cases = [(0, 1, 1, 64, 0), (0, 2, 2, 64, 0), (3, 6, 3, 32, 0), (0, 7, 1, 16, PCT_DROP_NO_GRAPH),
+             (5, 20, 2, 0, 0), (0, -1, 1, 8, PCT_DROP_NO_GRAPH)]
+    for begin, end, iters, lanes, flags in cases:
+        say(f"  fused vs separate: blocks [{begin},{end}) iters={iters} lanes={lanes} flags={flags}")
+        xs = x0.clone()
+        api.pct_drop_iterate(plan, pr, b, xs, block=c.block, lam=c.lam, n_iter=iters, block_begin=begin,
+                             block_end=end, lanes=lanes, flags=flags | PCT_DROP_SEPARATE_COMMIT)
+        xf = x0.clone()
+        api.pct_drop_iterate(plan, pr, b, xf, block=c.block, lam=c.lam, n_iter=iters, block_begin=begin,
+                             block_end=end, lanes=lanes, flags=flags)
+        torch.cuda.synchronize()
+        assert torch.equal(xs, xf), (xs - xf).abs().max().item()
+        assert not torch.equal(xf, x0)
+    # the fused sweep leaves its accumulators clear: a following FP64 run on
+    # the same workspace still matches the oracle
+    xd = torch.ones(sc.grid.nvox, dtype=torch.float64, device=DEV)
+    api.pct_drop_iterate(plan, pr, b, xd, block=c.block, lam=c.lam, n_iter=1, block_end=4)
+    ref = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=c.block, lam=c.lam, n_iter=1, blk_end=4)
+    assert rsp_close(xd.cpu().numpy(), ref, 0) <= 1e-10
+    # and the fused path itself against the oracle on a short run
+    xf = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+    api.pct_drop_iterate(plan, pr, b, xf, block=c.block, lam=c.lam, n_iter=1, block_end=5, lanes=64)
+    ref = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=c.block, lam=c.lam, n_iter=1, blk_end=5)
+    assert rsp_close(xf.double().cpu().numpy(), ref, 0) <= 1e-5
+    assert_status_clean(plan)
+
+
+# ---------------------------------------------------------------------------
+# differentiation form: gradient checks and the gradient-descent driver
+# ---------------------------------------------------------------------------
+def test_objective_gradient_central_differences():
+    # central differences (h = 1e-3) of the TV-regularised objective at 64
+    # seeded voxels, FP64 projections: the quadratic term is exact up to rounding
+    sc = scan(5, 20000)
+    plan, pr = gpu_setup(sc)
+    b = torch.from_numpy(sc.b).to(DEV)
+    beta, eps, h = 1e-3, 1e-3, 1e-3
+    x = torch.from_numpy(np.random.default_rng(21).uniform(0.8, 1.2, sc.grid.nvox)).to(DEV)
+    xg = x.clone().requires_grad_(True)
+    loss = api.tv_objective(plan, pr, b, xg, beta, eps)
+    (g,) = torch.autograd.grad(loss, xg)
+    # voxels the scan actually reaches
+    touched = torch.nonzero(api.pct_backproject(plan, pr, torch.ones(sc.m, dtype=torch.float64, device=DEV)) > 0)
+    pick = touched[torch.randperm(len(touched), generator=torch.Generator().manual_seed(3))[:64]].flatten()
+    worst = 0.0
+    for v in pick.tolist():
+        e = torch.zeros_like(x)
+        e[v] = h
+        with torch.no_grad():
+            lp = float(api.tv_objective(plan, pr, b, x + e, beta, eps))
+            lm = float(api.tv_objective(plan, pr, b, x - e, beta, eps))
+        fd = (lp - lm) / (2 * h)
+        worst = max(worst, abs(fd - float(g[v])) / max(abs(fd), 1e-3))
+    say(f"  FD vs autograd (FP64), 64 voxels: max rel {worst:.2e}")
+    assert worst < 1e-5
+
+
+def test_gradient_descent_matches_oracle():
+    sc = scan(5, 20000)
+    plan, pr = gpu_setup(sc)
+    b = torch.from_numpy(sc.b).to(DEV)
+    beta, eps, steps = 1e-3, 1e-3, 5
+    v0 = synth.power_start(sc.grid.nvox, seed=5)
+    lam_gpu = api.power_iteration(plan, pr, torch.from_numpy(v0).to(DEV), 20)
+    lam_orc = oracle.power_iteration(sc.grid, sc.mlp, sc.protons, v0, 20)
+    assert lam_gpu == pytest.approx(lam_orc, rel=1e-9)
+    eta = 1.0 / (lam_orc + 12 * beta / eps)
+    x0 = torch.ones(sc.grid.nvox, dtype=torch.float64, device=DEV)
+    x, losses, _ = api.tv_gradient_descent(plan, pr, b, x0, beta, eps, steps, eta=eta)
+    xr, lr = oracle.gradient_descent(sc.grid, sc.mlp, sc.protons, sc.b, np.ones(sc.grid.nvox), beta, eps, eta, steps)
+    np.testing.assert_allclose(losses, lr, rtol=1e-9)
+    np.testing.assert_allclose(x.cpu().numpy(), xr, rtol=1e-9, atol=1e-12)
+    assert losses[-1] < losses[0]
