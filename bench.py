@@ -12,6 +12,19 @@ dominant kernel (the fused block kernel) and the CPU oracle baseline measured
 on a bounded sample of the same scan.
 
     python bench.py [--gpus 1] [--steps 12] [--warmup 1] [--no-cpu-baseline]
+
+Two more workloads, each printing its own JSON line:
+    --config 4   precision form: 2*10^7 protons on the 200x200x32 scan, 8
+                 sweeps with FP32, FP16 and BF16 chords; RSP error of each
+                 against an FP64 run (FP64 value type and chords) and speed
+                 relative to the FP32-chord run.
+    --config 5   differentiation form: 2*10^7 protons on the 256x256x64 scan,
+                 20 steps of TV-regularised gradient descent (forward +
+                 backward projection per step); loss curve and pass rates.
+    --config alg1  the multi-region split (Algorithm 1) of the 10^7-proton
+                 200x200x32 scan into two overlapping z regions, run one after
+                 the other on this GPU, against the single-volume solve: insert
+                 RSP error after every sweep, per-region time.
 """
 from __future__ import annotations
 
@@ -68,6 +81,242 @@ def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks):
     }, float(err.max()), float(err.mean())
 
 
+def time_events(fn, reps=1):
+    """Mean ms of fn() on the current stream, bracketed by HIP events."""
+    import torch
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    z = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    z.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(z) / reps
+
+
+def parallel_sweep_ceiling(api, plan, pr, x):
+    """One forward projection (with ||a_i||^2) and one back projection over all
+    protons with no block sequencing: the rate the same walk reaches when every
+    proton is independent."""
+    import torch
+    r = torch.ones(pr.n, dtype=x.dtype, device=x.device)
+    g = torch.zeros_like(x)
+    api.pct_forward(plan, pr, x, with_norm=True)
+    api.pct_backproject(plan, pr, r, g)
+    f_ms = time_events(lambda: api.pct_forward(plan, pr, x, with_norm=True), reps=2)
+    b_ms = time_events(lambda: api.pct_backproject(plan, pr, r, g), reps=2)
+    log(f"[bench] parallel sweep: forward {f_ms:.1f} ms, back projection {b_ms:.1f} ms")
+    return {"forward_ms": f_ms, "backproject_ms": b_ms,
+            "protons_per_s_forward_plus_back": pr.n / ((f_ms + b_ms) * 1e-3)}
+
+
+def rsp_error(x, ref, touched):
+    import torch
+    d = (x.double() - ref.double()).abs() / ref.double().abs().clamp_min(1.0)
+    d = d[touched]
+    return float(d.max()), float(d.mean())
+
+
+def run_precision(args):
+    """Precision form on the 2*10^7-proton 200x200x32 scan."""
+    import torch
+    from paper_1802_01070_amd import api, synth
+    cfg = synth.CONFIGS[4]
+    m = args.protons or cfg.m
+    t0 = time.perf_counter()
+    sc = synth.make_scan(cfg, m=m)
+    log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
+    dev = "cuda:0"
+    plan = api.Plan(sc.grid, sc.mlp, dev)
+    pr = api.Protons(sc.protons, dev)
+    b = torch.from_numpy(sc.b).to(dev)
+    n_iter = cfg.n_iter
+    runs = {}
+    for name, dtype, chord in (("f64", torch.float64, "f64"), ("f32", torch.float32, "f32"),
+                               ("f16", torch.float32, "f16"), ("bf16", torch.float32, "bf16")):
+        x = torch.ones(sc.grid.nvox, dtype=dtype, device=dev)
+        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, chord=chord)  # warm-up
+        x.fill_(1.0)
+        ms = time_events(lambda: api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam,
+                                                      n_iter=n_iter, chord=chord))
+        bits = api.pct_device_status(plan)
+        log(f"[bench] {name} chords: {ms:.0f} ms for {n_iter} sweeps (status {bits:#x})")
+        runs[name] = (x, ms, bits)
+    ref = runs["f64"][0]
+    # voxels crossed by at least one row: A^T 1 > 0
+    cover = api.pct_backproject(plan, pr, torch.ones(pr.n, dtype=torch.float32, device=dev))
+    touched = cover > 0
+    table = {}
+    for name in ("f32", "f16", "bf16"):
+        x, ms, bits = runs[name]
+        emax, emean = rsp_error(x, ref, touched)
+        table[name] = {"ms_per_reconstruction": ms, "rsp_err_max": emax, "rsp_err_mean": emean,
+                       "speedup_vs_f32_chords": runs["f32"][1] / ms, "status": bits}
+    f16_ms = runs["f16"][1]
+    out = {
+        "metric": "proton-iterations/sec (fused MLP+DROP, FP16 chords) at 1 GPU",
+        "value": m * n_iter / (f16_ms * 1e-3),
+        "unit": "proton-iterations/s",
+        "n_gpus": 1, "steps": n_iter, "warmup": 1, "ms_per_step": f16_ms / n_iter,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f16 chords)",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {sc.grid.nx}x{sc.grid.ny}x{sc.grid.nz} grid, {m} protons, "
+                               f"{cfg.n_angles} angles, DROP block {cfg.block}, lambda {cfg.lam}, {n_iter} sweeps; "
+                               "chords rounded to FP16/BF16 as computed, FP32 iterate and accumulation, FP64 "
+                               "a_i.x and ||a_i||^2",
+                   "reference": "same scan, FP64 iterate and FP64 chords on the GPU",
+                   "touched_voxels": int(touched.sum())},
+        "precision": table,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_gradient(args):
+    """Differentiation form on the 2*10^7-proton 256x256x64 scan."""
+    import torch
+    from paper_1802_01070_amd import api, synth
+    cfg = synth.CONFIGS[5]
+    m = args.protons or cfg.m
+    t0 = time.perf_counter()
+    sc = synth.make_scan(cfg, m=m)
+    log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
+    dev = "cuda:0"
+    plan = api.Plan(sc.grid, sc.mlp, dev)
+    pr = api.Protons(sc.protons, dev)
+    b = torch.from_numpy(sc.b).to(dev)
+    beta, eps, n_steps = 1e-3, 1e-3, cfg.n_iter
+    x0 = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
+    r = torch.ones(pr.n, dtype=torch.float32, device=dev)
+    g = torch.zeros_like(x0)
+    api.pct_forward(plan, pr, x0)
+    api.pct_backproject(plan, pr, r, g)
+    f_ms = time_events(lambda: api.pct_forward(plan, pr, x0), reps=3)
+    b_ms = time_events(lambda: api.pct_backproject(plan, pr, r, g), reps=3)
+    v0 = torch.from_numpy(synth.power_start(sc.grid.nvox, cfg.seed)).to(dev, torch.float32)
+    t0 = time.perf_counter()
+    lam_max = api.power_iteration(plan, pr, v0, 20)
+    t_power = time.perf_counter() - t0
+    eta = 1.0 / (lam_max + 12.0 * beta / eps)
+    box = {}
+
+    def gd():
+        box["res"] = api.tv_gradient_descent(plan, pr, b, x0, beta, eps, n_steps, eta=eta)
+
+    gd_ms = time_events(gd)
+    x, losses, _ = box["res"]
+    bits = api.pct_device_status(plan)
+    log(f"[bench] forward {f_ms:.1f} ms, back projection {b_ms:.1f} ms, GD {gd_ms:.0f} ms; "
+        f"loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    out = {
+        "metric": "proton-iterations/sec (TV-regularised gradient descent, forward+backward) at 1 GPU",
+        "value": m * n_steps / (gd_ms * 1e-3),
+        "unit": "proton-iterations/s",
+        "n_gpus": 1, "steps": n_steps, "warmup": 1, "ms_per_step": gd_ms / n_steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {sc.grid.nx}x{sc.grid.ny}x{sc.grid.nz} grid, {m} protons, "
+                               f"{cfg.n_angles} angles, sorted by (angle, slab, t_in); {n_steps} gradient steps on "
+                               f"1/2||Ax-b||^2 + {beta} TV_eps (eps {eps}), step 1/(lambda_max + 12 beta/eps)",
+                   "beta": beta, "eps": eps},
+        "forward_protons_per_s": m / (f_ms * 1e-3),
+        "backward_protons_per_s": m / (b_ms * 1e-3),
+        "power_iteration": {"lambda_max": lam_max, "steps": 20, "seconds": t_power},
+        "eta": eta,
+        "loss_curve": losses,
+        "status": bits,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def insert_errors(sc, x):
+    """Per insert: mean RSP over voxels whose centre lies at least 1.5 mm
+    inside it, and its relative error (%) against the insert's true RSP."""
+    import torch
+    g = sc.grid
+    xs = g.origin[0] + (np.arange(g.nx) + 0.5) * g.pitch[0]
+    ys = g.origin[1] + (np.arange(g.ny) + 0.5) * g.pitch[1]
+    X, Y = np.meshgrid(xs, ys)
+    xv = x.double().cpu().numpy().reshape(g.nz, g.ny, g.nx)
+    out = []
+    for s in sc.phantom.inserts:
+        r = np.hypot(X - s.centre[0], Y - s.centre[1])
+        mask = r < s.axes[0] - 1.5
+        mean = float(xv[:, mask].mean())
+        out.append({"true": s.rsp, "mean": mean, "err_pct": 100.0 * (mean - s.rsp) / s.rsp})
+    return out
+
+
+def run_regions(args):
+    """Algorithm 1 on the 10^7-proton 200x200x32 scan against the single-volume
+    solve, sweep by sweep."""
+    import torch
+    from paper_1802_01070_amd import api, synth
+    cfg = synth.CONFIGS[2]
+    m = args.protons or cfg.m
+    n_sweeps = args.steps if args.steps != 12 else 6
+    t0 = time.perf_counter()
+    sc = synth.make_scan(cfg, m=m)
+    log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
+    dev = "cuda:0"
+    plan = api.Plan(sc.grid, sc.mlp, dev)
+    pr = api.Protons(sc.protons, dev)
+    b = torch.from_numpy(sc.b).to(dev)
+    hist = api.pct_slice_span_histogram(plan, pr)
+    halo = api.overlap_halo(hist, 0.96)
+    cov = (torch.cumsum(hist.double(), 0) / hist.sum()).cpu().numpy()
+    n_regions = 2
+    # single volume
+    x1 = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
+    api.pct_drop_iterate(plan, pr, b, x1, block=cfg.block, lam=cfg.lam, n_iter=1)   # warm-up
+    x1.fill_(1.0)
+    single = []
+    for k in range(n_sweeps):
+        ms = time_events(lambda: api.pct_drop_iterate(plan, pr, b, x1, block=cfg.block, lam=cfg.lam, n_iter=1))
+        single.append({"sweep": k + 1, "ms": ms, "inserts": insert_errors(sc, x1)})
+        log(f"[bench] single volume sweep {k + 1}: {ms:.0f} ms")
+    # two regions, one after the other on this GPU
+    x2 = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    state = None
+    lay = api.pct_region_layout(sc.grid.nz, n_regions, halo)
+    split = []
+    for k in range(n_sweeps):
+        torch.cuda.synchronize()
+        if state is None:
+            state = api.region_drop(plan, pr, b, x2, n_regions, halo, cfg.block, cfg.lam, 0)
+            for reg in state:     # warm-up sweep (records the graph), then back to x0 = 1
+                api.pct_drop_iterate(reg["plan"], reg["protons"], reg["b"], reg["x"], cfg.block, cfg.lam, 1)
+                reg["x"].fill_(1.0)
+        per_region = []
+        for reg in state:
+            per_region.append(time_events(lambda: api.pct_drop_iterate(reg["plan"], reg["protons"], reg["b"],
+                                                                          reg["x"], cfg.block, cfg.lam, 1)))
+        api.region_drop(plan, pr, b, x2, n_regions, halo, cfg.block, cfg.lam, 0, regions=state)
+        split.append({"sweep": k + 1, "ms_per_region": per_region, "inserts": insert_errors(sc, x2)})
+        log(f"[bench] two regions sweep {k + 1}: {per_region} ms")
+    torch.cuda.synchronize()
+    diff = (x1.double() - x2.double()).abs()
+    out = {
+        "metric": "proton-iterations/sec (Algorithm 1, two z regions, max over regions) at 1 GPU",
+        "value": m * n_sweeps / (max(sum(r["ms_per_region"][i] for r in split) for i in range(n_regions)) * 1e-3),
+        "unit": "proton-iterations/s",
+        "n_gpus": 1, "steps": n_sweeps, "warmup": 1,
+        "ms_per_step": float(np.mean([max(r["ms_per_region"]) for r in split])),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {sc.grid.nx}x{sc.grid.ny}x{sc.grid.nz} grid, {m} protons, "
+                               f"{cfg.n_angles} angles, DROP block {cfg.block}, lambda {cfg.lam}; {n_regions} z "
+                               f"regions with {halo} slices of halo (96% coverage), regions run one after the "
+                               "other; value = the rate a region-per-GPU run would reach (slowest region)",
+                   "layout": lay, "region_protons": [reg["protons"].n for reg in state]},
+        "coverage_by_span": [float(c) for c in cov[:12]],
+        "single_volume": single,
+        "regions": split,
+        "max_abs_diff_split_vs_single": float(diff.max()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +340,12 @@ def main():
     from paper_1802_01070_amd._lib import PCT_DROP_PROFILE
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.config == "4":
+        return run_precision(args)
+    if args.config == "5":
+        return run_gradient(args)
+    if args.config == "alg1":
+        return run_regions(args)
     key = int(args.config) if args.config.isdigit() else args.config
     cfg = synth.CONFIGS[key]
     m = args.protons or cfg.m
@@ -149,6 +404,8 @@ def main():
     log(f"[bench] {ms_per_step:.1f} ms/step, block kernel avg {k_avg_ms * 1e3:.2f} us ({k_n} sampled), "
         f"separate commit avg {c_avg_ms * 1e3:.2f} us ({c_n} sampled); host wall {t_host:.2f} s")
 
+    ceiling = parallel_sweep_ceiling(api, plan, pr, x)
+
     out = {
         "metric": "proton-iterations/sec (fused MLP+DROP) at 1 GPU",
         "value": value,
@@ -188,6 +445,7 @@ def main():
             "separate_commit_avg_us": c_avg_ms * 1e3 if c_n else None,
         },
         "cpu_baseline": None,
+        "parallel_sweep_ceiling": ceiling,
     }
     if not args.no_cpu_baseline:
         nb = min(args.cpu_blocks, T)

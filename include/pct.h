@@ -207,6 +207,57 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
 int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
            void *ws, size_t ws_bytes, void *stream);
 
+/* ---- multi-region reconstruction (Algorithm 1, Section II) ---------------
+ * The volume is cut along z into overlapping slab regions; each proton goes to
+ * every region holding both its entry slice (of v_in) and its exit slice (of
+ * v_out); every region is solved on its own (any entry point above, on a
+ * region plan); each slice of the final image is taken from the region whose
+ * core (non-overlapped part) holds it (selectSlice). */
+
+/* Writable SoA proton arrays of `capacity` records (device memory). */
+typedef struct {
+    float *t_in, *v_in, *th_in, *ph_in, *t_out, *v_out, *th_out, *ph_out, *gantry;
+    int64_t capacity;
+} pct_protons_buf;
+
+/* Host only.  Region r of n_regions: core slices [core_lo[r], core_hi[r]] =
+ * [floor(r nz / R), floor((r+1) nz / R) - 1]; region slices [z_lo[r],
+ * z_hi[r]] = the core extended by `halo` slices past every interior core
+ * boundary (the overlap of two neighbours is 2*halo slices).  Arrays of
+ * n_regions int32 (host memory).  Needs 1 <= n_regions <= nz, halo >= 0. */
+int pct_region_layout(int32_t nz, int32_t n_regions, int32_t halo, int32_t *z_lo, int32_t *z_hi, int32_t *core_lo,
+                      int32_t *core_hi);
+
+/* Host only.  A plan for slices z_lo..z_hi of the parent's grid (same x-y
+ * extent and MLP model, z origin moved up by z_lo slices). */
+int pct_plan_region(const pct_plan *parent, int32_t z_lo, int32_t z_hi, pct_plan **out);
+
+/* Step 2 of Algorithm 1 for one region: the records (and b) of the protons
+ * whose entry and exit slices both lie in [z_lo, z_hi] of the plan's grid are
+ * copied, in input order, to out (and b_out if b != NULL).  A slice is
+ * floor((v - origin_z) / pitch_z) in FP64, clamped to [0, nz-1]; a record
+ * with non-finite v_in or v_out belongs to no region.  *count (device
+ * int64[1]) receives the number of members; records past out->capacity are
+ * not written (compare *count with the capacity after synchronising). */
+int pct_region_select(const pct_plan *plan, const pct_protons *p, const float *b, int32_t z_lo, int32_t z_hi,
+                      const pct_protons_buf *out, float *b_out, int64_t *count, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* Coverage statistics of the proton tracks (the quantity of Table I, which
+ * sets the overlap): hist[k] += number of protons whose entry and exit slices
+ * (as in pct_region_select) differ by k, k = 0..nz-1; records with non-finite
+ * v_in or v_out are not counted.  hist: device int64[nz], accumulated.
+ * PCT_ERR_UNSUPPORTED for nz > 16384. */
+int pct_slice_span_histogram(const pct_plan *plan, const pct_protons *p, int64_t *hist, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* selectSlice / region extraction: copies slices [z_first, z_first + z_count)
+ * of the plan's grid from volume src, whose first slice is src_z0, to volume
+ * dst, whose first slice is dst_z0 (x-y planes of nx*ny values of dtype).
+ * Needs src_z0 <= z_first, dst_z0 <= z_first, z_first + z_count <= nz. */
+int pct_select_slices(const pct_plan *plan, const void *src, int32_t src_z0, void *dst, int32_t dst_z0,
+                      int32_t z_first, int32_t z_count, int32_t dtype, void *stream);
+
 /* ---- diagnostics --------------------------------------------------------- */
 
 /* Kernel timing of the last pct_drop_iterate call made with PCT_DROP_PROFILE:

@@ -24,7 +24,9 @@ FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out"
 
 EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan_table", "pct_workspace_size",
            "pct_plan_upload", "pct_device_status", "pct_mlp_trace", "pct_forward", "pct_backproject",
-           "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read")
+           "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read",
+           "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
+           "pct_slice_span_histogram")
 
 
 class PctError(RuntimeError):
@@ -45,6 +47,10 @@ class pct_mlp(C.Structure):
 
 class pct_protons(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in FIELDS] + [("n", C.c_int64)]
+
+
+class pct_protons_buf(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in FIELDS] + [("capacity", C.c_int64)]
 
 
 class pct_drop_opts(C.Structure):
@@ -80,6 +86,12 @@ def lib() -> C.CDLL:
             "pct_status_string": ([C.c_int], C.c_char_p),
             "pct_last_hip_error": ([], C.c_int),
             "pct_profile_read": ([vp, P(C.c_double), P(i64)], C.c_int),
+            "pct_region_layout": ([i32, i32, i32, P(i32), P(i32), P(i32), P(i32)], C.c_int),
+            "pct_plan_region": ([vp, i32, i32, P(vp)], C.c_int),
+            "pct_region_select": ([vp, P(pct_protons), vp, i32, i32, P(pct_protons_buf), vp, vp, vp, sz, vp],
+                                  C.c_int),
+            "pct_select_slices": ([vp, vp, i32, vp, i32, i32, i32, i32, vp], C.c_int),
+            "pct_slice_span_histogram": ([vp, P(pct_protons), vp, vp, sz, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -111,6 +123,10 @@ def make_mlp(mlp) -> pct_mlp:
 def make_protons(ptrs: dict, n: int) -> pct_protons:
     """ptrs: field -> device address (int)."""
     return pct_protons(*[C.c_void_p(int(ptrs[k])) for k in FIELDS], int(n))
+
+
+def make_protons_buf(ptrs: dict, capacity: int) -> pct_protons_buf:
+    return pct_protons_buf(*[C.c_void_p(int(ptrs[k])) for k in FIELDS], int(capacity))
 
 
 def make_opts(block: int, lam: float, n_iter: int, dtype: int, chord: str = "f64", flags: int = 0,

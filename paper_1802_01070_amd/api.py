@@ -42,14 +42,16 @@ def _dev(t: torch.Tensor, what: str, dtype=None, numel: Optional[int] = None):
 class Plan:
     """A pct_plan plus its device workspace (uploaded once)."""
 
-    def __init__(self, grid, mlp, device="cuda:0", n_hint: int = 0):
+    def __init__(self, grid, mlp, device="cuda:0", n_hint: int = 0, _handle: Optional[C.c_void_p] = None):
         self.grid = grid
         self.mlp = mlp
         self.device = torch.device(device)
         self.nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
-        h = C.c_void_p()
-        check(lib().pct_plan_create(C.byref(_lib.make_grid(grid)), C.byref(_lib.make_mlp(mlp)), C.byref(h)),
-              "pct_plan_create")
+        h = _handle
+        if h is None:
+            h = C.c_void_p()
+            check(lib().pct_plan_create(C.byref(_lib.make_grid(grid)), C.byref(_lib.make_mlp(mlp)), C.byref(h)),
+                  "pct_plan_create")
         self.handle = h
         k = C.c_int32()
         check(lib().pct_plan_segments(h, C.byref(k)), "pct_plan_segments")
@@ -61,6 +63,16 @@ class Plan:
         off = (-self.ws.data_ptr()) % 256
         self.ws_ptr = C.c_void_p(self.ws.data_ptr() + off)
         check(lib().pct_plan_upload(h, self.ws_ptr, self.ws_bytes, _stream(self.device)), "pct_plan_upload")
+
+    def region(self, z_lo: int, z_hi: int) -> "Plan":
+        """Plan of slices z_lo..z_hi of this grid (pct_plan_region)."""
+        import dataclasses
+        h = C.c_void_p()
+        check(lib().pct_plan_region(self.handle, int(z_lo), int(z_hi), C.byref(h)), "pct_plan_region")
+        o = self.grid.origin
+        g = dataclasses.replace(self.grid, nz=int(z_hi) - int(z_lo) + 1,
+                                origin=(o[0], o[1], o[2] + int(z_lo) * self.grid.pitch[2]))
+        return Plan(g, self.mlp, self.device, _handle=h)
 
     def table(self):
         import numpy as np
@@ -220,6 +232,92 @@ class TVFn(torch.autograd.Function):
     def backward(ctx, gout):
         (grad,) = ctx.saved_tensors
         return gout * grad, None, None
+
+
+def pct_region_layout(nz: int, n_regions: int, halo: int):
+    """[(z_lo, z_hi, core_lo, core_hi)] per region (host call)."""
+    arrs = [(C.c_int32 * n_regions)() for _ in range(4)] if n_regions > 0 else [None] * 4
+    check(lib().pct_region_layout(int(nz), int(n_regions), int(halo), *arrs), "pct_region_layout")
+    return [tuple(int(a[r]) for a in arrs) for r in range(n_regions)]
+
+
+def pct_region_select(plan: Plan, p: Protons, b: Optional[torch.Tensor], z_lo: int, z_hi: int):
+    """Records (and b) of the protons whose entry and exit slices lie in
+    [z_lo, z_hi], in input order: (Protons, b or None)."""
+    dev = plan.device
+    bufs = {k: torch.empty(p.n, dtype=torch.float32, device=dev) for k in FIELDS}
+    b_out = torch.empty(p.n, dtype=torch.float32, device=dev) if b is not None else None
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    out = _lib.make_protons_buf({k: v.data_ptr() for k, v in bufs.items()}, p.n)
+    bp = _dev(b, "b", dtype=torch.float32, numel=p.n) if b is not None else None
+    st = lib().pct_region_select(plan.handle, C.byref(p.s), bp, int(z_lo), int(z_hi), C.byref(out),
+                                 C.c_void_p(b_out.data_ptr()) if b_out is not None else None,
+                                 C.c_void_p(count.data_ptr()), plan.ws_ptr, plan.ws_bytes, _stream(dev))
+    check(st, "pct_region_select")
+    n = int(count.item())
+    sub = Protons({k: v[:n] for k, v in bufs.items()}, device=dev)
+    return sub, (b_out[:n] if b_out is not None else None)
+
+
+def pct_select_slices(plan: Plan, src: torch.Tensor, src_z0: int, dst: torch.Tensor, dst_z0: int, z_first: int,
+                      z_count: int):
+    code = _dtype_code(src)
+    if dst.dtype != src.dtype:
+        raise TypeError("src and dst differ in dtype")
+    plane = int(plan.grid.nx) * int(plan.grid.ny)
+    sp = _dev(src, "src")
+    dp = _dev(dst, "dst")
+    if src.numel() < (z_first - src_z0 + z_count) * plane or dst.numel() < (z_first - dst_z0 + z_count) * plane:
+        raise ValueError("volume too small for the requested slices")
+    st = lib().pct_select_slices(plan.handle, sp, int(src_z0), dp, int(dst_z0), int(z_first), int(z_count), code,
+                                 _stream(src.device))
+    check(st, "pct_select_slices")
+    return dst
+
+
+def pct_slice_span_histogram(plan: Plan, p: Protons) -> torch.Tensor:
+    """int64[nz]: protons per |exit slice - entry slice|."""
+    hist = torch.zeros(plan.grid.nz, dtype=torch.int64, device=plan.device)
+    st = lib().pct_slice_span_histogram(plan.handle, C.byref(p.s), C.c_void_p(hist.data_ptr()), plan.ws_ptr,
+                                        plan.ws_bytes, _stream(plan.device))
+    check(st, "pct_slice_span_histogram")
+    return hist
+
+
+def overlap_halo(hist: torch.Tensor, target: float = 0.96) -> int:
+    """Smallest k with at least `target` of the counted protons spanning <= k
+    slices (each region then reaches k slices past its core)."""
+    c = torch.cumsum(hist.double().cpu(), 0)
+    tot = float(c[-1])
+    if tot <= 0:
+        return 0
+    return int(torch.nonzero(c >= target * tot)[0, 0])
+
+
+def region_drop(plan: Plan, p: Protons, b: torch.Tensor, x: torch.Tensor, n_regions: int, halo: int, block: int,
+                lam: float, n_iter: int, chord: str = "f64", lanes: int = 0, regions=None):
+    """Algorithm 1 with DROP as the per-region solver, the regions run one
+    after the other on this GPU.  x (the full volume) holds the initial iterate
+    and receives the stitched result.  `regions` may carry the per-region
+    state of an earlier call (plans and selected protons) to continue the
+    iterations; returns it."""
+    lay = pct_region_layout(plan.grid.nz, n_regions, halo)
+    if regions is None:
+        regions = []
+        for z_lo, z_hi, c_lo, c_hi in lay:
+            rp = plan.region(z_lo, z_hi)
+            sub, b_sub = pct_region_select(plan, p, b, z_lo, z_hi)
+            xr = torch.empty(rp.nvox, dtype=x.dtype, device=x.device)
+            pct_select_slices(plan, x, 0, xr, z_lo, z_lo, z_hi - z_lo + 1)     # region's initial iterate
+            regions.append({"layout": (z_lo, z_hi, c_lo, c_hi), "plan": rp, "protons": sub, "b": b_sub, "x": xr})
+    for reg in regions:
+        if reg["protons"].n:
+            pct_drop_iterate(reg["plan"], reg["protons"], reg["b"], reg["x"], block, lam, n_iter, chord=chord,
+                             lanes=lanes)
+    for reg in regions:                                                      # selectSlice
+        z_lo, _, c_lo, c_hi = reg["layout"]
+        pct_select_slices(plan, reg["x"], z_lo, x, 0, c_lo, c_hi - c_lo + 1)
+    return regions
 
 
 class DropSolver:

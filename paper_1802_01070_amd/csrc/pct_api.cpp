@@ -1,6 +1,7 @@
 // Host side of the C ABI: plan construction (MLP coefficient table in FP64),
 // argument validation and dispatch to the HIP launchers.  Every check runs
 // before anything is enqueued on the device.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -374,6 +375,84 @@ int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, doubl
     int st = check_ws(plan, ws, ws_bytes, dtype);
     if (st) return st;
     return hip_status(launch_tv(*plan, x, dtype, eps, value_dev, grad, ws, stream));
+}
+
+int pct_region_layout(int32_t nz, int32_t n_regions, int32_t halo, int32_t *z_lo, int32_t *z_hi, int32_t *core_lo,
+                      int32_t *core_hi)
+{
+    if (nz < 1 || n_regions < 1 || n_regions > nz || halo < 0) return PCT_ERR_INVALID_ARG;
+    if (!z_lo || !z_hi || !core_lo || !core_hi) return PCT_ERR_INVALID_ARG;
+    for (int32_t r = 0; r < n_regions; ++r) {
+        const int32_t c0 = int32_t(int64_t(r) * nz / n_regions);
+        const int32_t c1 = int32_t(int64_t(r + 1) * nz / n_regions) - 1;
+        core_lo[r] = c0;
+        core_hi[r] = c1;
+        z_lo[r] = r > 0 ? std::max<int32_t>(0, c0 - halo) : 0;
+        z_hi[r] = r < n_regions - 1 ? int32_t(std::min<int64_t>(nz - 1, int64_t(c1) + halo)) : nz - 1;
+    }
+    return PCT_OK;
+}
+
+int pct_plan_region(const pct_plan *parent, int32_t z_lo, int32_t z_hi, pct_plan **out)
+{
+    if (!parent || !out) return PCT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (z_lo < 0 || z_hi < z_lo || z_hi >= parent->grid.nz) return PCT_ERR_INVALID_ARG;
+    pct_grid g = parent->grid;
+    g.nz = z_hi - z_lo + 1;
+    g.origin[2] = parent->grid.origin[2] + double(z_lo) * parent->grid.pitch[2];
+    return pct_plan_create(&g, &parent->mlp, out);
+}
+
+int pct_region_select(const pct_plan *plan, const pct_protons *p, const float *b, int32_t z_lo, int32_t z_hi,
+                      const pct_protons_buf *out, float *b_out, int64_t *count, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    if (!plan || !out || !count) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (z_lo < 0 || z_hi < z_lo || z_hi >= plan->grid.nz) return PCT_ERR_INVALID_ARG;
+    if (out->capacity < 0) return PCT_ERR_INVALID_ARG;
+    if (out->capacity > 0) {
+        float *ptrs[9] = {out->t_in, out->v_in, out->th_in, out->ph_in, out->t_out, out->v_out, out->th_out,
+                          out->ph_out, out->gantry};
+        for (float *q : ptrs)
+            if (!q) return PCT_ERR_INVALID_ARG;
+        if (b && !b_out) return PCT_ERR_INVALID_ARG;
+    }
+    st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    ProtonsBufDev o{out->t_in, out->v_in, out->th_in, out->ph_in, out->t_out, out->v_out, out->th_out, out->ph_out,
+                    out->gantry};
+    return hip_status(launch_region_select(*plan, protons_dev(p), p->n, b, z_lo, z_hi, o, out->capacity,
+                                           b ? b_out : nullptr, count, ws, stream));
+}
+
+int pct_slice_span_histogram(const pct_plan *plan, const pct_protons *p, int64_t *hist, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    if (!plan || !hist) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (plan->grid.nz > 16384) return PCT_ERR_UNSUPPORTED;  // bins live in LDS
+    st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    if (p->n == 0) return PCT_OK;
+    return hip_status(launch_span_histogram(*plan, protons_dev(p), p->n, hist, stream));
+}
+
+int pct_select_slices(const pct_plan *plan, const void *src, int32_t src_z0, void *dst, int32_t dst_z0,
+                      int32_t z_first, int32_t z_count, int32_t dtype, void *stream)
+{
+    if (!plan || !valid_dtype(dtype) || z_count < 0) return PCT_ERR_INVALID_ARG;
+    if (src_z0 < 0 || dst_z0 < 0 || z_first < src_z0 || z_first < dst_z0) return PCT_ERR_INVALID_ARG;
+    if (int64_t(z_first) + z_count > plan->grid.nz) return PCT_ERR_INVALID_ARG;
+    if (z_count == 0) return PCT_OK;
+    if (!src || !dst) return PCT_ERR_INVALID_ARG;
+    const size_t plane = size_t(plan->grid.nx) * size_t(plan->grid.ny) * (dtype == PCT_F64 ? 8 : 4);
+    const char *s = static_cast<const char *>(src) + size_t(z_first - src_z0) * plane;
+    char *d = static_cast<char *>(dst) + size_t(z_first - dst_z0) * plane;
+    return hip_status(copy_device(d, s, size_t(z_count) * plane, stream));
 }
 
 const char *pct_status_string(int status)

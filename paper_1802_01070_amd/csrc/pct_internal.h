@@ -27,6 +27,10 @@ struct ProtonsDev {
     const float *t_in, *v_in, *th_in, *ph_in, *t_out, *v_out, *th_out, *ph_out, *gantry;
 };
 
+struct ProtonsBufDev {
+    float *t_in, *v_in, *th_in, *ph_in, *t_out, *v_out, *th_out, *ph_out, *gantry;
+};
+
 // Workspace layout (byte offsets from the workspace base).
 struct Layout {
     size_t hdr;      // status word and counters (256 B)
@@ -78,6 +82,11 @@ int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const
                        void *ws, void *stream);
 int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x,
                 const pct_drop_opts &o, void *ws, void *stream);
+int launch_span_histogram(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *hist, void *stream);
+int copy_device(void *dst, const void *src, size_t bytes, void *stream);
+int launch_region_select(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, int z_lo, int z_hi,
+                         const ProtonsBufDev &out, int64_t capacity, float *b_out, int64_t *count, void *ws,
+                         void *stream);
 int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,
               void *stream);
 int upload_table(const pct_plan &pl, void *ws, void *stream);

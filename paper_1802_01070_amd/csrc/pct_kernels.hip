@@ -901,6 +901,134 @@ __global__ void __launch_bounds__(kWG) k_sum_partials(const double *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// region selection (Algorithm 1, step 2): stable compaction of the records
+// whose entry and exit slices lie in [z_lo, z_hi].  Each of G workgroups owns
+// a contiguous chunk of the input: count, exclusive scan of the G counts,
+// then an ordered scatter (wave ballots) inside every chunk.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int slice_index(float v, const GridDev &g)
+{
+    const double d = double(v);
+    if (!isfinite(d)) return -1;
+    const double s = floor((d - g.lo[2]) / g.pitch[2]);
+    return int(fmin(fmax(s, 0.0), double(g.n[2] - 1)));
+}
+
+__device__ __forceinline__ bool region_member(const ProtonsDev &p, int64_t i, const GridDev &g, int z_lo, int z_hi)
+{
+    const int a = slice_index(p.v_in[i], g);
+    const int c = slice_index(p.v_out[i], g);
+    return a >= z_lo && a <= z_hi && c >= z_lo && c <= z_hi;
+}
+
+constexpr int kSelWG = 256;
+
+// histogram of |exit slice - entry slice|: LDS bins per workgroup, then one
+// global atomic per non-empty bin
+__global__ void __launch_bounds__(kSelWG) k_span_histogram(ProtonsDev p, int64_t n, GridDev g,
+                                                            unsigned long long *hist)
+{
+    extern __shared__ unsigned int bins[];
+    const int nz = g.n[2];
+    for (int k = threadIdx.x; k < nz; k += kSelWG) bins[k] = 0u;
+    __syncthreads();
+    for (int64_t i = int64_t(blockIdx.x) * kSelWG + threadIdx.x; i < n; i += int64_t(gridDim.x) * kSelWG) {
+        const int a = slice_index(p.v_in[i], g);
+        const int c = slice_index(p.v_out[i], g);
+        if (a >= 0 && c >= 0) atomicAdd(&bins[a > c ? a - c : c - a], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nz; k += kSelWG)
+        if (bins[k]) atomicAdd(hist + k, static_cast<unsigned long long>(bins[k]));
+}
+
+__global__ void __launch_bounds__(kSelWG) k_region_count(ProtonsDev p, int64_t n, int64_t chunk, GridDev g,
+                                                          int z_lo, int z_hi, long long *partial)
+{
+    __shared__ long long red[kSelWG / 64];
+    const int64_t a = int64_t(blockIdx.x) * chunk;
+    const int64_t e = min(n, a + chunk);
+    long long c = 0;
+    for (int64_t i = a + threadIdx.x; i < e; i += kSelWG) c += region_member(p, i, g, z_lo, z_hi) ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int w = 0; w < kSelWG / 64; ++w) t += red[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of G <= kMaxPartials counts in place; total to *count
+__global__ void __launch_bounds__(kSelWG) k_region_scan(long long *partial, int G, int64_t *count)
+{
+    __shared__ long long run[kSelWG];
+    const int per = (G + kSelWG - 1) / kSelWG;
+    const int a = int(threadIdx.x) * per;
+    const int e = min(G, a + per);
+    long long s = 0;
+    for (int k = a; k < e; ++k) s += partial[k];
+    run[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        for (int t = 0; t < kSelWG; ++t) {
+            const long long v = run[t];
+            run[t] = acc;
+            acc += v;
+        }
+        *count = acc;
+    }
+    __syncthreads();
+    long long acc = run[threadIdx.x];
+    for (int k = a; k < e; ++k) {
+        const long long v = partial[k];
+        partial[k] = acc;
+        acc += v;
+    }
+}
+
+__global__ void __launch_bounds__(kSelWG) k_region_scatter(ProtonsDev p, const float *b, int64_t n, int64_t chunk,
+                                                            GridDev g, int z_lo, int z_hi, const long long *partial,
+                                                            ProtonsBufDev out, int64_t capacity, float *b_out)
+{
+    __shared__ int wave_cnt[kSelWG / 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t a = int64_t(blockIdx.x) * chunk;
+    const int64_t e = min(n, a + chunk);
+    long long base = partial[blockIdx.x];
+    for (int64_t t0 = a; t0 < e; t0 += kSelWG) {
+        const int64_t i = t0 + threadIdx.x;
+        const bool f = i < e && region_member(p, i, g, z_lo, z_hi);
+        const unsigned long long mask = __ballot(f);
+        if (lane == 0) wave_cnt[wave] = __popcll(mask);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < kSelWG / 64; ++w) {
+            before += w < wave ? wave_cnt[w] : 0;
+            total += wave_cnt[w];
+        }
+        const long long dst = base + before + __popcll(mask & ((1ull << lane) - 1ull));
+        if (f && dst < capacity) {
+            out.t_in[dst] = p.t_in[i];
+            out.v_in[dst] = p.v_in[i];
+            out.th_in[dst] = p.th_in[i];
+            out.ph_in[dst] = p.ph_in[i];
+            out.t_out[dst] = p.t_out[i];
+            out.v_out[dst] = p.v_out[i];
+            out.th_out[dst] = p.th_out[i];
+            out.ph_out[dst] = p.ph_out[i];
+            out.gantry[dst] = p.gantry[i];
+            if (b_out) b_out[dst] = b[i];
+        }
+        base += total;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline char *wsb(void *ws) { return static_cast<char *>(ws); }
@@ -1281,6 +1409,39 @@ int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (o.dtype == PCT_F64) return drop_dispatch_chord<double>(pl, p, n, b, static_cast<double *>(x), o, ws, s);
     return drop_dispatch_chord<float>(pl, p, n, b, static_cast<float *>(x), o, ws, s);
+}
+
+int launch_span_histogram(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *hist, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const GridDev g = grid_dev(pl.grid);
+    const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(2048, (n + kSelWG - 1) / kSelWG)));
+    hipLaunchKernelGGL(k_span_histogram, dim3(grid), dim3(kSelWG), size_t(pl.grid.nz) * sizeof(unsigned), s, p, n, g,
+                       reinterpret_cast<unsigned long long *>(hist));
+    return hipGetLastError();
+}
+
+int copy_device(void *dst, const void *src, size_t bytes, void *stream)
+{
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+}
+
+int launch_region_select(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, int z_lo, int z_hi,
+                         const ProtonsBufDev &out, int64_t capacity, float *b_out, int64_t *count, void *ws,
+                         void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    long long *partial = reinterpret_cast<long long *>(wsb(ws) + L.partial);
+    const GridDev g = grid_dev(pl.grid);
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(kMaxPartials, (n + kSelWG - 1) / kSelWG));
+    int64_t chunk = (n + G - 1) / G;
+    chunk = std::max<int64_t>(kSelWG, (chunk + kSelWG - 1) / kSelWG * kSelWG);
+    hipLaunchKernelGGL(k_region_count, dim3(unsigned(G)), dim3(kSelWG), 0, s, p, n, chunk, g, z_lo, z_hi, partial);
+    hipLaunchKernelGGL(k_region_scan, dim3(1), dim3(kSelWG), 0, s, partial, int(G), count);
+    hipLaunchKernelGGL(k_region_scatter, dim3(unsigned(G)), dim3(kSelWG), 0, s, p, b, n, chunk, g, z_lo, z_hi,
+                       partial, out, capacity, b_out);
+    return hipGetLastError();
 }
 
 int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,

@@ -191,6 +191,51 @@ def test_tv_validation(plan):
     assert L.pct_tv(plan, C.c_void_p(8), 0, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -2
 
 
+def test_region_layout_matches_the_papers_example():
+    import json
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "alg1_two_regions_20_slices.json")))
+    from paper_1802_01070_amd import api
+    lay = api.pct_region_layout(g["nz"], g["n_regions"], g["overlap"] // 2)
+    assert [[a, b] for a, b, _, _ in lay] == g["regions"]
+    assert [[c, d] for _, _, c, d in lay] == g["owned"]
+    from oracle import regions
+    for args in ((20, 2, 3), (32, 4, 2), (7, 7, 0), (33, 5, 40), (64, 3, 9)):
+        assert api.pct_region_layout(*args) == regions.layout(*args)
+    L = _lib.lib()
+    a = (C.c_int32 * 4)()
+    for bad in ((0, 1, 0), (5, 0, 0), (5, 6, 0), (5, 2, -1)):
+        assert L.pct_region_layout(*bad, a, a, a, a) == -1
+    assert L.pct_region_layout(5, 1, 0, None, a, a, a) == -1
+
+
+def test_plan_region_and_region_calls_validate(plan):
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.pct_plan_region(plan, -1, 1, C.byref(h)) == -1
+    assert L.pct_plan_region(plan, 1, 0, C.byref(h)) == -1
+    assert L.pct_plan_region(plan, 0, 2, C.byref(h)) == -1          # the fixture grid has nz = 2
+    assert L.pct_plan_region(plan, 1, 1, C.byref(h)) == 0
+    np.testing.assert_array_equal(table_of(h), table_of(plan))     # same MLP model
+    L.pct_plan_destroy(h)
+    p = fake_protons(100)
+    nb = ws_size(plan)
+    buf = _lib.make_protons_buf({k: 0x9000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, 100)
+    cnt = C.c_void_p(0xA000)
+    sel = L.pct_region_select
+    assert sel(plan, C.byref(p), None, 1, 0, C.byref(buf), None, cnt, FAKE_WS, nb, None) == -1
+    assert sel(plan, C.byref(p), None, 0, 2, C.byref(buf), None, cnt, FAKE_WS, nb, None) == -1
+    assert sel(plan, C.byref(p), None, 0, 1, C.byref(buf), None, None, FAKE_WS, nb, None) == -1
+    assert sel(plan, C.byref(p), C.c_void_p(0xB000), 0, 1, C.byref(buf), None, cnt, FAKE_WS, nb, None) == -1
+    assert sel(plan, C.byref(p), None, 0, 1, C.byref(buf), None, cnt, FAKE_WS, nb, None) == -2   # not uploaded
+    ss = L.pct_select_slices
+    v = C.c_void_p(0xC000)
+    assert ss(plan, v, 0, v, 0, 0, 3, 0, None) == -1                 # past nz
+    assert ss(plan, v, 1, v, 0, 0, 1, 0, None) == -1                 # src starts after z_first
+    assert ss(plan, v, 0, v, 0, 0, 1, 4, None) == -1                 # dtype
+    assert ss(plan, None, 0, v, 0, 0, 1, 0, None) == -1
+    assert ss(plan, v, 0, v, 0, 1, 0, 0, None) == 0                  # nothing to copy
+
+
 def test_status_strings():
     for st in range(-7, 1):
         s = _lib.status_string(st)
