@@ -72,6 +72,7 @@ extern "C" {
 #define PCT_DEV_NONFINITE 0x2u
 #define PCT_DEV_REENTRY 0x4u
 #define PCT_DEV_ACC_RANGE 0x8u /* a DROP contribution beyond the FP32 accumulator's fixed-point range */
+#define PCT_DEV_BAD_ROW 0x10u  /* a stored row names a voxel outside the plan's grid (piece skipped) */
 
 /* ---- value and chord types --------------------------------------------- */
 typedef enum {
@@ -206,6 +207,45 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
  * FP64) and, if grad != NULL, its gradient.  x, grad: dtype[nvox]. */
 int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
            void *ws, size_t ws_bytes, void *stream);
+
+/* ---- stored rows (precision form) ----------------------------------------
+ * The precision form lets the chord lengths be stored rather than recomputed.
+ * With 288 GB of HBM the rows of the scans here fit (10^7 protons x ~257
+ * pieces x 6 B = 15 GB with FP16 chords), so each row is traced once and the
+ * DROP sweeps read it back.  Rows are CSR in device memory owned by the
+ * caller: piece k of row i is at offsets[i] + k, in path order (the emission
+ * list after consecutive merge); vox holds the voxel index, with bit 31 set
+ * on the first piece of each distinct voxel of the row (so the row counts
+ * once in s_j); chord holds the merged chord rounded to chord_type; n2 holds
+ * ||a_i||^2 of the rounded row (re-entries summed per voxel first) in FP64. */
+typedef struct {
+    const int64_t *offsets; /* n + 1 */
+    const int32_t *vox;     /* offsets[n] */
+    const void *chord;      /* offsets[n] values: float (PCT_CHORD_F32) or FP16 / BF16 bit patterns (uint16) */
+    const double *n2;       /* n */
+    int64_t n;
+    int32_t chord_type;     /* PCT_CHORD_F32, PCT_CHORD_F16 or PCT_CHORD_BF16 */
+    int32_t reserved;       /* must be 0 */
+} pct_rows;
+
+/* Row lengths and their prefix sums: offsets[0] = 0, offsets[i+1] =
+ * offsets[i] + (pieces of row i).  offsets: device int64[n+1]. */
+int pct_rows_count(const pct_plan *plan, const pct_protons *p, int64_t *offsets, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* Traces every row into the CSR arrays laid out by pct_rows_count (vox:
+ * int32[offsets[n]], chord: offsets[n] values of chord_type, n2: double[n]).
+ * A row whose length differs from its offsets raises PCT_DEV_ROW_OVERFLOW
+ * (pieces past its end are not written). */
+int pct_rows_build(const pct_plan *plan, const pct_protons *p, int32_t chord_type, const int64_t *offsets,
+                   int32_t *vox, void *chord, double *n2, void *ws, size_t ws_bytes, void *stream);
+
+/* Block-iterative DROP over stored rows: as pct_drop_iterate, with the rows
+ * read instead of traced.  FP32 x only (PCT_ERR_UNSUPPORTED otherwise);
+ * opts->chord must equal rows->chord_type; opts->lanes: 0 (64), 16, 32 or 64
+ * lanes per row; PCT_DROP_SEPARATE_COMMIT is not supported. */
+int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const float *b, void *x,
+                          const pct_drop_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- multi-region reconstruction (Algorithm 1, Section II) ---------------
  * The volume is cut along z into overlapping slab regions; each proton goes to

@@ -19,14 +19,14 @@ PCT_DROP_CHECK_FINITE = 0x1
 PCT_DROP_NO_GRAPH = 0x2
 PCT_DROP_PROFILE = 0x4
 PCT_DROP_SEPARATE_COMMIT = 0x8
-DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range"}
+DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range", 0x10: "bad_row"}
 FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out", "gantry")
 
 EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan_table", "pct_workspace_size",
            "pct_plan_upload", "pct_device_status", "pct_mlp_trace", "pct_forward", "pct_backproject",
            "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read",
            "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
-           "pct_slice_span_histogram")
+           "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows")
 
 
 class PctError(RuntimeError):
@@ -51,6 +51,11 @@ class pct_protons(C.Structure):
 
 class pct_protons_buf(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in FIELDS] + [("capacity", C.c_int64)]
+
+
+class pct_rows(C.Structure):
+    _fields_ = [("offsets", C.c_void_p), ("vox", C.c_void_p), ("chord", C.c_void_p), ("n2", C.c_void_p),
+                ("n", C.c_int64), ("chord_type", C.c_int32), ("reserved", C.c_int32)]
 
 
 class pct_drop_opts(C.Structure):
@@ -92,6 +97,9 @@ def lib() -> C.CDLL:
                                   C.c_int),
             "pct_select_slices": ([vp, vp, i32, vp, i32, i32, i32, i32, vp], C.c_int),
             "pct_slice_span_histogram": ([vp, P(pct_protons), vp, vp, sz, vp], C.c_int),
+            "pct_rows_count": ([vp, P(pct_protons), vp, vp, sz, vp], C.c_int),
+            "pct_rows_build": ([vp, P(pct_protons), i32, vp, vp, vp, vp, vp, sz, vp], C.c_int),
+            "pct_drop_iterate_rows": ([vp, P(pct_rows), vp, vp, P(pct_drop_opts), vp, sz, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

@@ -170,6 +170,50 @@ def pct_drop_iterate(plan: Plan, p: Protons, b: torch.Tensor, x: torch.Tensor, b
     return x
 
 
+class Rows:
+    """Stored CSR rows of a proton set (pct_rows_count + pct_rows_build):
+    chord lengths in FP32, FP16 or BF16, traced once on the GPU."""
+
+    _CHORD_DTYPE = {"f32": torch.float32, "f16": torch.int16, "bf16": torch.int16}
+
+    def __init__(self, plan: Plan, p: Protons, chord: str = "f16"):
+        if chord not in self._CHORD_DTYPE:
+            raise ValueError("stored chords are f32, f16 or bf16")
+        dev = plan.device
+        self.n = p.n
+        self.chord_name = chord
+        self.offsets = torch.empty(p.n + 1, dtype=torch.int64, device=dev)
+        st = lib().pct_rows_count(plan.handle, C.byref(p.s), C.c_void_p(self.offsets.data_ptr()), plan.ws_ptr,
+                                  plan.ws_bytes, _stream(dev))
+        check(st, "pct_rows_count")
+        self.nnz = int(self.offsets[-1].item())
+        self.vox = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        self.chord = torch.empty(max(self.nnz, 1), dtype=self._CHORD_DTYPE[chord], device=dev)
+        self.n2 = torch.empty(max(p.n, 1), dtype=torch.float64, device=dev)
+        st = lib().pct_rows_build(plan.handle, C.byref(p.s), _lib.CHORDS[chord], C.c_void_p(self.offsets.data_ptr()),
+                                  C.c_void_p(self.vox.data_ptr()), C.c_void_p(self.chord.data_ptr()),
+                                  C.c_void_p(self.n2.data_ptr()), plan.ws_ptr, plan.ws_bytes, _stream(dev))
+        check(st, "pct_rows_build")
+        self.s = _lib.pct_rows(self.offsets.data_ptr(), self.vox.data_ptr(), self.chord.data_ptr(),
+                               self.n2.data_ptr(), self.n, _lib.CHORDS[chord], 0)
+
+    @property
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in (self.offsets, self.vox, self.chord, self.n2))
+
+
+def pct_drop_iterate_rows(plan: Plan, rows: Rows, b: torch.Tensor, x: torch.Tensor, block: int, lam: float,
+                          n_iter: int, flags: int = 0, block_begin: int = 0, block_end: int = -1, lanes: int = 0):
+    code = _dtype_code(x)
+    bp = _dev(b, "b", dtype=torch.float32, numel=rows.n)
+    xp = _dev(x, "x", numel=plan.nvox)
+    o = _lib.make_opts(block, lam, n_iter, code, rows.chord_name, flags, block_begin, block_end, lanes)
+    st = lib().pct_drop_iterate_rows(plan.handle, C.byref(rows.s), bp, xp, C.byref(o), plan.ws_ptr, plan.ws_bytes,
+                                     _stream(x.device))
+    check(st, "pct_drop_iterate_rows")
+    return x
+
+
 def pct_tv(plan: Plan, x: torch.Tensor, eps: float, with_grad: bool = True):
     code = _dtype_code(x)
     xp = _dev(x, "x", numel=plan.nvox)

@@ -377,6 +377,59 @@ int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, doubl
     return hip_status(launch_tv(*plan, x, dtype, eps, value_dev, grad, ws, stream));
 }
 
+int pct_rows_count(const pct_plan *plan, const pct_protons *p, int64_t *offsets, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    if (!plan || !offsets) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    return hip_status(launch_rows_count(*plan, protons_dev(p), p->n, offsets, ws, stream));
+}
+
+static bool stored_chord_type(int32_t c) { return c == PCT_CHORD_F32 || c == PCT_CHORD_F16 || c == PCT_CHORD_BF16; }
+
+int pct_rows_build(const pct_plan *plan, const pct_protons *p, int32_t chord_type, const int64_t *offsets,
+                   int32_t *vox, void *chord, double *n2, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !stored_chord_type(chord_type)) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (p->n > 0 && (!offsets || !vox || !chord || !n2)) return PCT_ERR_INVALID_ARG;
+    st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    if (p->n == 0) return PCT_OK;
+    return hip_status(launch_rows_build(*plan, protons_dev(p), p->n, chord_type, offsets, vox, chord, n2, ws, stream));
+}
+
+int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const float *b, void *x,
+                          const pct_drop_opts *o, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!plan || !rows || !o || !x) return PCT_ERR_INVALID_ARG;
+    if (rows->n < 0 || rows->n > (int64_t(1) << 40) || rows->reserved != 0) return PCT_ERR_INVALID_ARG;
+    if (!stored_chord_type(rows->chord_type)) return PCT_ERR_INVALID_ARG;
+    if (rows->n > 0 && (!rows->offsets || !rows->vox || !rows->chord || !rows->n2 || !b)) return PCT_ERR_INVALID_ARG;
+    if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
+    if (o->chord != rows->chord_type) return PCT_ERR_INVALID_ARG;
+    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT))
+        return PCT_ERR_INVALID_ARG;
+    if (o->block >= (int64_t(1) << 20)) return PCT_ERR_INVALID_ARG;
+    if (o->lanes != 0 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64) return PCT_ERR_INVALID_ARG;
+    if (o->reserved != 0) return PCT_ERR_INVALID_ARG;
+    if (o->dtype != PCT_F32 || (o->flags & PCT_DROP_SEPARATE_COMMIT)) return PCT_ERR_UNSUPPORTED;
+    int64_t T = rows->n > 0 ? (rows->n + o->block - 1) / o->block : 0;
+    int64_t end = o->block_end < 0 ? T : o->block_end;
+    if (o->block_begin < 0 || end > T || o->block_begin > end) return PCT_ERR_INVALID_ARG;
+    int st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    if (o->n_iter == 0 || o->block_begin == end) return PCT_OK;
+    pct_drop_opts oo = *o;
+    oo.block_end = end;
+    return hip_status(launch_drop_rows(*const_cast<pct_plan *>(plan), *rows, b, static_cast<float *>(x), oo, ws,
+                                       stream));
+}
+
 int pct_region_layout(int32_t nz, int32_t n_regions, int32_t halo, int32_t *z_lo, int32_t *z_hi, int32_t *core_lo,
                       int32_t *core_hi)
 {

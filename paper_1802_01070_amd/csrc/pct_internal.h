@@ -82,6 +82,11 @@ int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const
                        void *ws, void *stream);
 int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x,
                 const pct_drop_opts &o, void *ws, void *stream);
+int launch_rows_count(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *offsets, void *ws, void *stream);
+int launch_rows_build(const pct_plan &pl, const ProtonsDev &p, int64_t n, int chord_type, const int64_t *offsets,
+                      int32_t *vox, void *chord, double *n2, void *ws, void *stream);
+int launch_drop_rows(pct_plan &pl, const pct_rows &rows, const float *b, float *x, const pct_drop_opts &o, void *ws,
+                     void *stream);
 int launch_span_histogram(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *hist, void *stream);
 int copy_device(void *dst, const void *src, size_t bytes, void *stream);
 int launch_region_select(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, int z_lo, int z_hi,

@@ -10,6 +10,7 @@
 //   k_drop_rows    the same with one lane per proton (very long paths)
 //   k_drop_commit  x_j += acc_j / s_j over the touched range, reset
 //   k_tv           smoothed total variation value and gradient
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -978,7 +979,7 @@ __global__ void __launch_bounds__(kSelWG) k_region_scan(long long *partial, int 
             run[t] = acc;
             acc += v;
         }
-        *count = acc;
+        if (count) *count = acc;
     }
     __syncthreads();
     long long acc = run[threadIdx.x];
@@ -1026,6 +1027,255 @@ __global__ void __launch_bounds__(kSelWG) k_region_scatter(ProtonsDev p, const f
         base += total;
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// stored rows (precision form): trace once, sweep from the stored CSR rows
+// ---------------------------------------------------------------------------
+// Counting sink: merged pieces of a row.
+struct CountSink {
+    int32_t n;
+    __device__ __forceinline__ void segment(double, double) {}
+    __device__ __forceinline__ void final(int, int, int, int, double) { ++n; }
+};
+
+// Row lengths (after consecutive merge) into offsets[1..n].
+__global__ void __launch_bounds__(kWG) k_row_lengths(ProtonsDev p, int64_t n, long long *len_out,
+                                                     const double *__restrict__ tab, int K, GridDev g,
+                                                     unsigned *status)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Rec r = load_rec(p, i);
+    CountSink cs{0};
+    if (rec_finite(r)) {
+        Merge<CountSink, PCT_CHORD_F64> m(cs, g);
+        walk_path(r, tab, K, g, m);
+        m.finish();
+    } else {
+        raise_status(status, PCT_DEV_NONFINITE);
+    }
+    len_out[i] = cs.n;
+}
+
+// chunk sums of v[0..n) (G chunks of `chunk` values)
+__global__ void __launch_bounds__(kSelWG) k_chunk_sums(const long long *v, int64_t n, int64_t chunk,
+                                                        long long *partial)
+{
+    __shared__ long long red[kSelWG / 64];
+    const int64_t a = int64_t(blockIdx.x) * chunk;
+    const int64_t e = min(n, a + chunk);
+    long long c = 0;
+    for (int64_t i = a + threadIdx.x; i < e; i += kSelWG) c += v[i];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int w = 0; w < kSelWG / 64; ++w) t += red[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// in-place inclusive scan of every chunk, offset by the chunk's exclusive base
+__global__ void __launch_bounds__(kSelWG) k_chunk_scan(long long *v, int64_t n, int64_t chunk,
+                                                        const long long *partial)
+{
+    __shared__ long long tile[kSelWG];
+    const int64_t a = int64_t(blockIdx.x) * chunk;
+    const int64_t e = min(n, a + chunk);
+    long long base = partial[blockIdx.x];
+    for (int64_t t0 = a; t0 < e; t0 += kSelWG) {
+        const int64_t i = t0 + threadIdx.x;
+        tile[threadIdx.x] = i < e ? v[i] : 0;
+        __syncthreads();
+        for (int d = 1; d < kSelWG; d <<= 1) {
+            const long long add = int(threadIdx.x) >= d ? tile[threadIdx.x - d] : 0;
+            __syncthreads();
+            tile[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < e) v[i] = base + tile[threadIdx.x];
+        base += tile[kSelWG - 1];
+        __syncthreads();
+    }
+}
+
+// Stored chord formats.
+template <int CT>
+struct StoredChord;
+template <>
+struct StoredChord<PCT_CHORD_F32> {
+    using type = float;
+    __device__ static __forceinline__ float put(double c) { return float(c); }
+    __device__ static __forceinline__ float get(float v) { return v; }
+};
+template <>
+struct StoredChord<PCT_CHORD_F16> {
+    using type = unsigned short;
+    __device__ static __forceinline__ unsigned short put(double c)
+    {
+        // c is already an FP16 value: the conversion is exact
+        return __half_as_ushort(__float2half(float(c)));
+    }
+    __device__ static __forceinline__ float get(unsigned short v) { return __half2float(__ushort_as_half(v)); }
+};
+template <>
+struct StoredChord<PCT_CHORD_BF16> {
+    using type = unsigned short;
+    __device__ static __forceinline__ unsigned short put(double c)
+    {
+        // c is already a BF16 value: its float has 16 zero low bits
+        return static_cast<unsigned short>(__float_as_uint(float(c)) >> 16);
+    }
+    __device__ static __forceinline__ float get(unsigned short v) { return __uint_as_float(unsigned(v) << 16); }
+};
+
+template <int CT>
+struct RowSink {
+    using S = StoredChord<CT>;
+    int32_t *vox;
+    typename S::type *ch;
+    int64_t pos, end;
+    Reentry re;
+    double n2;
+    __device__ __forceinline__ void segment(double dx, double dy) { re.segment(dx, dy); }
+    __device__ __forceinline__ void final(int j, int ix, int iy, int iz, double c)
+    {
+        bool first;
+        const double aprev = re.visit(j, ix, iy, iz, c, first);
+        n2 += c * (2.0 * aprev + c);
+        if (pos < end) {
+            vox[pos] = first ? int(unsigned(j) | 0x80000000u) : j;
+            ch[pos] = S::put(c);
+        }
+        ++pos;
+    }
+};
+
+template <int CT>
+__global__ void __launch_bounds__(kWG) k_rows_build(ProtonsDev p, int64_t n, const long long *__restrict__ offsets,
+                                                    int32_t *vox, typename StoredChord<CT>::type *chord, double *n2,
+                                                    const double *__restrict__ tab, int K, GridDev g,
+                                                    unsigned *status)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Rec r = load_rec(p, i);
+    RowSink<CT> rs{vox, chord, offsets[i], offsets[i + 1], {}, 0.0};
+    rs.re.init(r);
+    if (rec_finite(r)) {
+        Merge<RowSink<CT>, CT> m(rs, g);
+        walk_path(r, tab, K, g, m);
+        m.finish();
+        if (rs.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
+    } else {
+        raise_status(status, PCT_DEV_NONFINITE);
+    }
+    if (rs.pos != rs.end) raise_status(status, PCT_DEV_ROW_OVERFLOW);  // offsets from other records
+    n2[i] = rs.n2;
+}
+
+struct RowsDev {
+    const long long *offsets;
+    const int32_t *vox;
+    const void *chord;
+    const double *n2;
+};
+
+constexpr int kRowRegs = 8;  // pieces per lane kept in registers between the gather and the scatter
+
+// Fused FP32 DROP block over stored rows: LPR lanes per row, 64 / LPR rows per
+// one-wave workgroup; commit workgroups first (see k_drop_fused).
+template <int CT, int LPR>
+__global__ void __launch_bounds__(64) k_drop_rows_fused(RowsDev rows, const float *__restrict__ b,
+                                                        const float *__restrict__ base, float *__restrict__ next,
+                                                        const unsigned long long *__restrict__ pk_prev,
+                                                        unsigned long long *pk_cur, unsigned long long *pk_old,
+                                                        int *r_cur, const int *r_prev, const int *r_old,
+                                                        int *r_reset, int64_t lo, int64_t hi, double lambda,
+                                                        unsigned *status, int nvox)
+{
+    if (int(blockIdx.x) < kCommitWG) {
+        commit_part(base, next, pk_prev, pk_old, r_prev, r_old, r_reset, nvox, int(blockIdx.x), kCommitWG);
+        return;
+    }
+    using S = StoredChord<CT>;
+    const typename S::type *__restrict__ chord = static_cast<const typename S::type *>(rows.chord);
+    constexpr int RPW = 64 / LPR;
+    const int lane = threadIdx.x;
+    const int l = lane % LPR;
+    const int64_t i = lo + int64_t(blockIdx.x - kCommitWG) * RPW + lane / LPR;
+    bool active = i < hi;
+    int64_t a = 0, e = 0;
+    double bi = 0.0, n2 = 0.0;
+    if (active) {
+        a = rows.offsets[i];
+        e = rows.offsets[i + 1];
+        bi = double(b[i]);
+        n2 = rows.n2[i];
+        if (!isfinite(bi)) {
+            if (l == 0) raise_status(status, PCT_DEV_NONFINITE);
+            active = false;
+        }
+    }
+    if (!active) e = a;
+    const LazyX xa{base, pk_prev};
+    int jr[kRowRegs];
+    float cr[kRowRegs];
+    double dot = 0.0;
+    // a piece naming a voxel outside the grid (rows built for another
+    // plan) is dropped: chord 0 and voxel 0
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kRowRegs; ++k) {
+        const int64_t q = a + l + int64_t(k) * LPR;
+        jr[k] = 0;
+        cr[k] = 0.f;
+        if (q < e) {
+            const int v = rows.vox[q];
+            if ((v & 0x7FFFFFFF) < nvox) {
+                jr[k] = v;
+                cr[k] = S::get(chord[q]);
+            } else {
+                bad = true;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kRowRegs; ++k)
+        if (a + l + int64_t(k) * LPR < e) dot += double(cr[k]) * xa(jr[k] & 0x7FFFFFFF);
+    for (int64_t q = a + l + int64_t(kRowRegs) * LPR; q < e; q += LPR) {
+        const int j = rows.vox[q] & 0x7FFFFFFF;
+        if (j < nvox)
+            dot += double(S::get(chord[q])) * xa(j);
+        else
+            bad = true;
+    }
+    if (bad) raise_status(status, PCT_DEV_BAD_ROW);
+    dot = group_sum<LPR>(dot);
+    int jmin = INT_MAX, jmax = -1;
+    if (active && n2 > 0.0) {
+        const double rho = lambda * (bi - dot) / n2;
+#pragma unroll
+        for (int k = 0; k < kRowRegs; ++k) {
+            if (a + l + int64_t(k) * LPR < e) {
+                const int j = jr[k] & 0x7FFFFFFF;
+                atomicAdd(pk_cur + j, pack_contribution(rho * double(cr[k]), jr[k] < 0, status));
+                jmin = min(jmin, j);
+                jmax = max(jmax, j);
+            }
+        }
+        for (int64_t q = a + l + int64_t(kRowRegs) * LPR; q < e; q += LPR) {
+            const int v = rows.vox[q];
+            const int j = v & 0x7FFFFFFF;
+            if (j >= nvox) continue;
+            atomicAdd(pk_cur + j, pack_contribution(rho * double(S::get(chord[q])), v < 0, status));
+            jmin = min(jmin, j);
+            jmax = max(jmax, j);
+        }
+    }
+    publish_range(jmin, jmax, r_cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -1248,116 +1498,85 @@ void graph_release(pct_plan &pl)
     pl.capture_stream = nullptr;
 }
 
-template <typename T, int CHORD>
-static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
-                     const pct_drop_opts &o, void *ws, hipStream_t s)
+// Buffers of the fused FP32 schedule: X[0] = x, X[1] in the workspace,
+// accumulators PK[0..2], range slots R[0..3] (header words from kHdrSlots).
+struct FusedBufs {
+    float *X[2];
+    unsigned long long *PK[3];
+    int *R[4];
+    int nv;
+    unsigned copy_grid;
+};
+
+static FusedBufs fused_bufs(const pct_plan &pl, void *ws, float *x)
 {
-    const bool prof = (o.flags & PCT_DROP_PROFILE) != 0;
-    if (prof) {
-        hipError_t e = prof_prepare(pl);
-        if (e != hipSuccess) return e;
-    }
-    const int lanes = choose_lanes(pl, o.lanes);
-    const int64_t nblk = o.block_end - o.block_begin;
-    const int64_t every = std::max<int64_t>(1, (nblk + kProfSamples - 1) / kProfSamples);
-    Layout L = layout_for(pl.nvox, pl.K, o.dtype);
-    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
-    unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
+    const Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    FusedBufs F;
+    F.X[0] = x;
+    F.X[1] = reinterpret_cast<float *>(wsb(ws) + L.x1);
+    for (int k = 0; k < 3; ++k)
+        F.PK[k] = reinterpret_cast<unsigned long long *>(wsb(ws) + L.acc + size_t(k) * L.acc_stride);
     int *hdr = reinterpret_cast<int *>(wsb(ws) + L.hdr);
-    void *acc = wsb(ws) + L.acc;
-    int32_t *cnt = reinterpret_cast<int32_t *>(wsb(ws) + L.cnt);
-    GridDev g = grid_dev(pl.grid);
-    const unsigned commit_grid = unsigned(std::min<int64_t>(4096, (pl.nvox + kWG - 1) / kWG));
+    for (int k = 0; k < 4; ++k) F.R[k] = hdr + kHdrSlots + 2 * k;
+    F.nv = int(pl.nvox);
+    F.copy_grid = unsigned(std::min<int64_t>(2048, (pl.nvox + 255) / 256));
+    return F;
+}
 
-    // One sweep: re-arm the range words, then block kernel + commit per block.
-    // Profiling samples one sweep's launches evenly.
-    auto enqueue_sweep = [&](hipStream_t s, bool record_events) {
-        hipLaunchKernelGGL(k_reset_ranges, dim3(1), dim3(64), 0, s, hdr);
-        int64_t seq = 0;
-        for (int64_t t = o.block_begin; t < o.block_end; ++t, ++seq) {
-            int64_t lo = t * o.block;
-            int64_t hi = std::min<int64_t>(n, lo + o.block);
-            int *r_this = hdr + (seq % 2 == 0 ? kHdrRange0 : kHdrRange1);
-            int *r_next = hdr + (seq % 2 == 0 ? kHdrRange1 : kHdrRange0);
-            const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
-            if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
-            launch_block<T, CHORD>(lanes, s, p, b, x, acc, cnt, r_this, tab, pl.K, g, lo, hi, o.lambda, status);
-            if (sample) {
-                (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
-                pl.prof_used[0]++;
-                (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1]), s);
-            }
-            hipLaunchKernelGGL(k_drop_commit<T>, dim3(commit_grid), dim3(kWG), 0, s, x, acc, cnt, r_this, r_next);
-            if (sample) {
-                (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1] + 1), s);
-                pl.prof_used[1]++;
-            }
+// Arguments of the launch at position q of a fused sweep (see k_drop_fused).
+struct FusedStep {
+    const float *base;
+    float *next;
+    const unsigned long long *pk_prev;
+    unsigned long long *pk_cur, *pk_old;
+    int *r_cur;
+    const int *r_prev, *r_old;
+    int *r_reset;
+};
+
+static FusedStep fused_step(const FusedBufs &F, int64_t q)
+{
+    return FusedStep{F.X[q % 2],       F.X[(q + 1) % 2], F.PK[(q + 2) % 3], F.PK[q % 3],      F.PK[(q + 1) % 3],
+                     F.R[q % 4],       F.R[(q + 3) % 4], F.R[(q + 2) % 4],  F.R[(q + 1) % 4]};
+}
+
+// One fused sweep over blocks [b0, b1): copy, one launch per block (launch_q
+// enqueues the kernel of block [lo, hi) at position q), flush.  Profiling
+// samples the per-block launches evenly.
+template <class LaunchQ>
+static void enqueue_fused(pct_plan &pl, const FusedBufs &F, int64_t b0, int64_t b1, int64_t block, int64_t n,
+                          hipStream_t s, bool record_events, int64_t every, LaunchQ launch_q)
+{
+    hipLaunchKernelGGL(k_sweep_begin, dim3(F.copy_grid), dim3(256), 0, s, F.X[0], F.X[1], F.R[0], F.nv);
+    int64_t q = 0;
+    for (int64_t t = b0; t < b1; ++t, ++q) {
+        const int64_t lo = t * block;
+        const int64_t hi = std::min<int64_t>(n, lo + block);
+        const bool sample = record_events && (q % every == 0) && pl.prof_used[0] < kProfSamples;
+        if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
+        launch_q(s, q, lo, hi, fused_step(F, q));
+        if (sample) {
+            (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
+            pl.prof_used[0]++;
         }
-    };
+    }
+    if (q > 0) {
+        const int64_t last = q - 1;
+        hipLaunchKernelGGL(k_sweep_end, dim3(F.copy_grid), dim3(256), 0, s, F.X[0], F.X[q % 2], F.PK[last % 3],
+                           F.PK[(last + 2) % 3], F.R[last % 4], F.R[(last + 3) % 4], F.nv);
+    }
+}
 
-    // Fused FP32 sweep: X[0] = x, X[1] in the workspace, accumulators PK[0..2],
-    // range slots R[0..3] (header words from kHdrSlots), all indexed by the
-    // block's position q in the sweep.
-    auto enqueue_fused_sweep = [&](hipStream_t s, bool record_events) {
-        if constexpr (sizeof(T) == 4) {
-            float *X[2] = {x, reinterpret_cast<float *>(wsb(ws) + L.x1)};
-            unsigned long long *PK[3];
-            for (int k = 0; k < 3; ++k)
-                PK[k] = reinterpret_cast<unsigned long long *>(wsb(ws) + L.acc + size_t(k) * L.acc_stride);
-            int *R[4];
-            for (int k = 0; k < 4; ++k) R[k] = hdr + kHdrSlots + 2 * k;
-            const int nv = int(pl.nvox);
-            const unsigned copy_grid = unsigned(std::min<int64_t>(2048, (pl.nvox + 255) / 256));
-            hipLaunchKernelGGL(k_sweep_begin, dim3(copy_grid), dim3(256), 0, s, X[0], X[1], R[0], nv);
-            int64_t q = 0;
-            for (int64_t t = o.block_begin; t < o.block_end; ++t, ++q) {
-                const int64_t lo = t * o.block;
-                const int64_t hi = std::min<int64_t>(n, lo + o.block);
-                const bool sample = record_events && (q % every == 0) && pl.prof_used[0] < kProfSamples;
-                if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
-                launch_fused<CHORD>(lanes, s, p, b, X[q % 2], X[(q + 1) % 2], PK[(q + 2) % 3], PK[q % 3],
-                                    PK[(q + 1) % 3], R[q % 4], R[(q + 3) % 4], R[(q + 2) % 4], R[(q + 1) % 4], tab,
-                                    pl.K, g, lo, hi, o.lambda, status, nv);
-                if (sample) {
-                    (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
-                    pl.prof_used[0]++;
-                }
-            }
-            if (q > 0) {
-                const int64_t last = q - 1;
-                hipLaunchKernelGGL(k_sweep_end, dim3(copy_grid), dim3(256), 0, s, X[0], X[q % 2], PK[last % 3],
-                                   PK[(last + 2) % 3], R[last % 4], R[(last + 3) % 4], nv);
-            }
-        } else {
-            (void)s;
-            (void)record_events;
-        }
-    };
-    const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT);
-    auto sweep = [&](hipStream_t s, bool record_events) {
-        if (fused)
-            enqueue_fused_sweep(s, record_events);
-        else
-            enqueue_sweep(s, record_events);
-    };
-
-    const bool use_graph = !(o.flags & PCT_DROP_NO_GRAPH) && !prof;
+// Runs n_iter sweeps: directly on the stream, or captured once into a HIP
+// graph (cached on the plan for an identical launch key) and replayed.
+template <class Sweep>
+static int run_sweeps(pct_plan &pl, const std::vector<uint64_t> &key, bool use_graph, int n_iter, bool prof,
+                      hipStream_t s, Sweep sweep)
+{
     if (!use_graph) {
-        for (int it = 0; it < o.n_iter; ++it) sweep(s, prof && it == o.n_iter - 1);
+        for (int it = 0; it < n_iter; ++it) sweep(s, prof && it == n_iter - 1);
         return hipGetLastError();
     }
-    // The sweep is captured once into a HIP graph and replayed; the graph is
-    // cached on the plan for identical launch arguments.
-    std::vector<uint64_t> key = {
-        reinterpret_cast<uint64_t>(p.t_in),   reinterpret_cast<uint64_t>(p.v_in),
-        reinterpret_cast<uint64_t>(p.th_in),  reinterpret_cast<uint64_t>(p.ph_in),
-        reinterpret_cast<uint64_t>(p.t_out),  reinterpret_cast<uint64_t>(p.v_out),
-        reinterpret_cast<uint64_t>(p.th_out), reinterpret_cast<uint64_t>(p.ph_out),
-        reinterpret_cast<uint64_t>(p.gantry), reinterpret_cast<uint64_t>(b),
-        reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
-        uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
-        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), uint64_t(fused), 0};
-    std::memcpy(&key.back(), &o.lambda, sizeof(double));
     if (!pl.graph_exec || pl.graph_key != key) {
         // recorded on a private stream (the caller's stream may be the null
         // stream, which cannot be captured); launched on the caller's stream
@@ -1384,11 +1603,93 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         pl.graph_exec = exec;
         pl.graph_key = key;
     }
-    for (int it = 0; it < o.n_iter; ++it) {
+    for (int it = 0; it < n_iter; ++it) {
         hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(pl.graph_exec), s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+static inline uint64_t bits_of(double v)
+{
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof(u));
+    return u;
+}
+
+template <typename T, int CHORD>
+static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
+                     const pct_drop_opts &o, void *ws, hipStream_t s)
+{
+    const bool prof = (o.flags & PCT_DROP_PROFILE) != 0;
+    if (prof) {
+        hipError_t e = prof_prepare(pl);
+        if (e != hipSuccess) return e;
+    }
+    const int lanes = choose_lanes(pl, o.lanes);
+    const int64_t nblk = o.block_end - o.block_begin;
+    const int64_t every = std::max<int64_t>(1, (nblk + kProfSamples - 1) / kProfSamples);
+    Layout L = layout_for(pl.nvox, pl.K, o.dtype);
+    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
+    int *hdr = reinterpret_cast<int *>(wsb(ws) + L.hdr);
+    void *acc = wsb(ws) + L.acc;
+    int32_t *cnt = reinterpret_cast<int32_t *>(wsb(ws) + L.cnt);
+    GridDev g = grid_dev(pl.grid);
+    const unsigned commit_grid = unsigned(std::min<int64_t>(4096, (pl.nvox + kWG - 1) / kWG));
+
+    // Separate schedule: re-arm the range words, then block kernel + commit
+    // per block.
+    auto enqueue_sweep = [&](hipStream_t s, bool record_events) {
+        hipLaunchKernelGGL(k_reset_ranges, dim3(1), dim3(64), 0, s, hdr);
+        int64_t seq = 0;
+        for (int64_t t = o.block_begin; t < o.block_end; ++t, ++seq) {
+            int64_t lo = t * o.block;
+            int64_t hi = std::min<int64_t>(n, lo + o.block);
+            int *r_this = hdr + (seq % 2 == 0 ? kHdrRange0 : kHdrRange1);
+            int *r_next = hdr + (seq % 2 == 0 ? kHdrRange1 : kHdrRange0);
+            const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
+            if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
+            launch_block<T, CHORD>(lanes, s, p, b, x, acc, cnt, r_this, tab, pl.K, g, lo, hi, o.lambda, status);
+            if (sample) {
+                (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
+                pl.prof_used[0]++;
+                (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1]), s);
+            }
+            hipLaunchKernelGGL(k_drop_commit<T>, dim3(commit_grid), dim3(kWG), 0, s, x, acc, cnt, r_this, r_next);
+            if (sample) {
+                (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1] + 1), s);
+                pl.prof_used[1]++;
+            }
+        }
+    };
+    const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT);
+    auto sweep = [&](hipStream_t s, bool record_events) {
+        if constexpr (sizeof(T) == 4) {
+            if (fused) {
+                const FusedBufs F = fused_bufs(pl, ws, x);
+                enqueue_fused(pl, F, o.block_begin, o.block_end, o.block, n, s, record_events, every,
+                              [&](hipStream_t s, int64_t, int64_t lo, int64_t hi, const FusedStep &f) {
+                                  launch_fused<CHORD>(lanes, s, p, b, f.base, f.next, f.pk_prev, f.pk_cur, f.pk_old,
+                                                      f.r_cur, f.r_prev, f.r_old, f.r_reset, tab, pl.K, g, lo, hi,
+                                                      o.lambda, status, F.nv);
+                              });
+                return;
+            }
+        }
+        enqueue_sweep(s, record_events);
+    };
+    const bool use_graph = !(o.flags & PCT_DROP_NO_GRAPH) && !prof;
+    std::vector<uint64_t> key = {
+        reinterpret_cast<uint64_t>(p.t_in),   reinterpret_cast<uint64_t>(p.v_in),
+        reinterpret_cast<uint64_t>(p.th_in),  reinterpret_cast<uint64_t>(p.ph_in),
+        reinterpret_cast<uint64_t>(p.t_out),  reinterpret_cast<uint64_t>(p.v_out),
+        reinterpret_cast<uint64_t>(p.th_out), reinterpret_cast<uint64_t>(p.ph_out),
+        reinterpret_cast<uint64_t>(p.gantry), reinterpret_cast<uint64_t>(b),
+        reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
+        uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
+        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), uint64_t(fused), bits_of(o.lambda), 0};
+    return run_sweeps(pl, key, use_graph, o.n_iter, prof, s, sweep);
 }
 
 template <typename T>
@@ -1442,6 +1743,125 @@ int launch_region_select(const pct_plan &pl, const ProtonsDev &p, int64_t n, con
     hipLaunchKernelGGL(k_region_scatter, dim3(unsigned(G)), dim3(kSelWG), 0, s, p, b, n, chunk, g, z_lo, z_hi,
                        partial, out, capacity, b_out);
     return hipGetLastError();
+}
+
+__global__ void k_zero_i64(long long *p, int64_t n)
+{
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+int launch_rows_count(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *offsets, void *ws, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
+    long long *partial = reinterpret_cast<long long *>(wsb(ws) + L.partial);
+    long long *off = reinterpret_cast<long long *>(offsets);
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, off, int64_t(1));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off + 1, tab, pl.K,
+                           grid_dev(pl.grid), status);
+        const int64_t G = std::max<int64_t>(1, std::min<int64_t>(kMaxPartials, (n + kSelWG - 1) / kSelWG));
+        int64_t chunk = (n + G - 1) / G;
+        chunk = std::max<int64_t>(kSelWG, (chunk + kSelWG - 1) / kSelWG * kSelWG);
+        hipLaunchKernelGGL(k_chunk_sums, dim3(unsigned(G)), dim3(kSelWG), 0, s, off + 1, n, chunk, partial);
+        hipLaunchKernelGGL(k_region_scan, dim3(1), dim3(kSelWG), 0, s, partial, int(G),
+                           static_cast<int64_t *>(nullptr));
+        hipLaunchKernelGGL(k_chunk_scan, dim3(unsigned(G)), dim3(kSelWG), 0, s, off + 1, n, chunk, partial);
+    }
+    return hipGetLastError();
+}
+
+int launch_rows_build(const pct_plan &pl, const ProtonsDev &p, int64_t n, int chord_type, const int64_t *offsets,
+                      int32_t *vox, void *chord, double *n2, void *ws, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
+    const long long *off = reinterpret_cast<const long long *>(offsets);
+    const GridDev g = grid_dev(pl.grid);
+    switch (chord_type) {
+    case PCT_CHORD_F16:
+        hipLaunchKernelGGL(k_rows_build<PCT_CHORD_F16>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<unsigned short *>(chord), n2, tab, pl.K, g, status);
+        break;
+    case PCT_CHORD_BF16:
+        hipLaunchKernelGGL(k_rows_build<PCT_CHORD_BF16>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<unsigned short *>(chord), n2, tab, pl.K, g, status);
+        break;
+    default:
+        hipLaunchKernelGGL(k_rows_build<PCT_CHORD_F32>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<float *>(chord), n2, tab, pl.K, g, status);
+    }
+    return hipGetLastError();
+}
+
+template <int CT>
+static void launch_rows_fused(int lanes, hipStream_t s, const RowsDev &rows, const float *b, const FusedStep &f,
+                              int64_t lo, int64_t hi, double lambda, unsigned *status, int nvox)
+{
+    const int64_t n = hi - lo;
+    switch (lanes) {
+#define PCT_LAUNCH_ROWS(LPR)                                                                                     \
+    case LPR: {                                                                                                  \
+        const unsigned grid = unsigned(kCommitWG + (n + (64 / LPR) - 1) / (64 / LPR));                        \
+        hipLaunchKernelGGL((k_drop_rows_fused<CT, LPR>), dim3(grid), dim3(64), 0, s, rows, b, f.base, f.next,     \
+                           f.pk_prev, f.pk_cur, f.pk_old, f.r_cur, f.r_prev, f.r_old, f.r_reset, lo, hi, lambda,  \
+                           status, nvox);                                                                        \
+        break;                                                                                                   \
+    }
+        PCT_LAUNCH_ROWS(16)
+        PCT_LAUNCH_ROWS(32)
+        PCT_LAUNCH_ROWS(64)
+#undef PCT_LAUNCH_ROWS
+    default: break;
+    }
+}
+
+int launch_drop_rows(pct_plan &pl, const pct_rows &rows, const float *b, float *x, const pct_drop_opts &o, void *ws,
+                     void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool prof = (o.flags & PCT_DROP_PROFILE) != 0;
+    if (prof) {
+        hipError_t e = prof_prepare(pl);
+        if (e != hipSuccess) return e;
+    }
+    const int lanes = o.lanes == 0 ? 64 : o.lanes;
+    const int64_t nblk = o.block_end - o.block_begin;
+    const int64_t every = std::max<int64_t>(1, (nblk + kProfSamples - 1) / kProfSamples);
+    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
+    const RowsDev rd{reinterpret_cast<const long long *>(rows.offsets), rows.vox, rows.chord, rows.n2};
+    const int64_t n = rows.n;
+    auto sweep = [&](hipStream_t s, bool record_events) {
+        const FusedBufs F = fused_bufs(pl, ws, x);
+        enqueue_fused(pl, F, o.block_begin, o.block_end, o.block, n, s, record_events, every,
+                      [&](hipStream_t s, int64_t, int64_t lo, int64_t hi, const FusedStep &f) {
+                          switch (rows.chord_type) {
+                          case PCT_CHORD_F16:
+                              launch_rows_fused<PCT_CHORD_F16>(lanes, s, rd, b, f, lo, hi, o.lambda, status, F.nv);
+                              break;
+                          case PCT_CHORD_BF16:
+                              launch_rows_fused<PCT_CHORD_BF16>(lanes, s, rd, b, f, lo, hi, o.lambda, status, F.nv);
+                              break;
+                          default:
+                              launch_rows_fused<PCT_CHORD_F32>(lanes, s, rd, b, f, lo, hi, o.lambda, status, F.nv);
+                          }
+                      });
+    };
+    const bool use_graph = !(o.flags & PCT_DROP_NO_GRAPH) && !prof;
+    std::vector<uint64_t> key = {reinterpret_cast<uint64_t>(rows.offsets), reinterpret_cast<uint64_t>(rows.vox),
+                                 reinterpret_cast<uint64_t>(rows.chord),   reinterpret_cast<uint64_t>(rows.n2),
+                                 reinterpret_cast<uint64_t>(b),            reinterpret_cast<uint64_t>(x),
+                                 reinterpret_cast<uint64_t>(ws),           uint64_t(n),
+                                 uint64_t(o.block),                        uint64_t(o.block_begin),
+                                 uint64_t(o.block_end),                    uint64_t(rows.chord_type),
+                                 uint64_t(lanes),                          bits_of(o.lambda),
+                                 1};
+    return run_sweeps(pl, key, use_graph, o.n_iter, prof, s, sweep);
 }
 
 int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,

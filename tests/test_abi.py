@@ -236,6 +236,36 @@ def test_plan_region_and_region_calls_validate(plan):
     assert ss(plan, v, 0, v, 0, 1, 0, 0, None) == 0                  # nothing to copy
 
 
+def test_stored_row_calls_validate(plan):
+    L = _lib.lib()
+    p = fake_protons(100)
+    nb = ws_size(plan)
+    v = C.c_void_p(0xD000)
+    assert L.pct_rows_count(plan, C.byref(p), None, FAKE_WS, nb, None) == -1
+    assert L.pct_rows_count(plan, C.byref(p), v, FAKE_WS, nb, None) == -2            # not uploaded
+    assert L.pct_rows_build(plan, C.byref(p), 0, v, v, v, v, FAKE_WS, nb, None) == -1  # FP64 chords are not stored
+    assert L.pct_rows_build(plan, C.byref(p), 2, None, v, v, v, FAKE_WS, nb, None) == -1
+    assert L.pct_rows_build(plan, C.byref(p), 2, v, v, v, v, FAKE_WS, nb, None) == -2
+    rows = _lib.pct_rows(0xE000, 0xE100, 0xE200, 0xE300, 100, 2, 0)
+    ok = _lib.make_opts(64, 0.1, 1, 0, chord="f16")
+    run = L.pct_drop_iterate_rows
+    assert run(plan, C.byref(rows), v, v, C.byref(ok), FAKE_WS, nb, None) == -2       # valid up to the workspace
+    for field, value in (("chord", 1), ("lanes", 8), ("block", 0), ("reserved", 1), ("flags", 0x10),
+                         ("block_end", 3)):
+        o = _lib.make_opts(64, 0.1, 1, 0, chord="f16")
+        setattr(o, field, value)
+        assert run(plan, C.byref(rows), v, v, C.byref(o), FAKE_WS, nb, None) == -1, field
+    for field, value in (("dtype", 1), ("flags", 0x8)):
+        o = _lib.make_opts(64, 0.1, 1, 0, chord="f16")
+        setattr(o, field, value)
+        assert run(plan, C.byref(rows), v, v, C.byref(o), FAKE_WS, nb, None) == -7, field
+    bad = _lib.pct_rows(0xE000, 0xE100, 0xE200, 0xE300, 100, 0, 0)                    # FP64 stored chords
+    assert run(plan, C.byref(bad), v, v, C.byref(ok), FAKE_WS, nb, None) == -1
+    bad = _lib.pct_rows(0xE000, 0, 0xE200, 0xE300, 100, 2, 0)
+    assert run(plan, C.byref(bad), v, v, C.byref(ok), FAKE_WS, nb, None) == -1
+    assert run(plan, C.byref(rows), None, v, C.byref(ok), FAKE_WS, nb, None) == -1
+
+
 def test_status_strings():
     for st in range(-7, 1):
         s = _lib.status_string(st)
