@@ -48,6 +48,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernel_sources_digest() -> str:
+    """sha256 over the HIP sources of the library (the traffic counters below
+    are valid only for the kernels they were taken on)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1802_01070_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".h", ".cpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the block kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload, or None when the kernel
+    sources changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "traffic_k_drop_fused_cfg2.json")
+    if not os.path.exists(p):
+        return None, "no counter summary"
+    t = json.load(open(p))
+    if t.get("workload") != workload:
+        return None, "counters taken on another workload"
+    if t.get("sources_sha256") != kernel_sources_digest():
+        return None, "kernel sources changed since the counters were taken"
+    return float(t["hbm_bytes_per_launch"]), p
+
+
 def count_nonzeros(api, plan, pr, chunk=1 << 20):
     """Sum over protons of the path's merged (voxel, chord) pieces, from the
     trace kernel (max_nnz = 1: only the lengths are kept)."""
@@ -144,6 +172,23 @@ def run_precision(args):
         bits = api.pct_device_status(plan)
         log(f"[bench] {name} chords: {ms:.0f} ms for {n_iter} sweeps (status {bits:#x})")
         runs[name] = (x, ms, bits)
+    # stored rows: traced once (timed), then the same sweeps read from HBM
+    stored = {}
+    for name in ("f32", "f16", "bf16"):
+        box = {}
+        build_ms = time_events(lambda: box.setdefault("rows", api.Rows(plan, pr, name)))
+        rows = box["rows"]
+        x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
+        api.pct_drop_iterate_rows(plan, rows, b, x, block=cfg.block, lam=cfg.lam, n_iter=1)   # warm-up
+        x.fill_(1.0)
+        ms = time_events(lambda: api.pct_drop_iterate_rows(plan, rows, b, x, block=cfg.block, lam=cfg.lam,
+                                                           n_iter=n_iter))
+        bits = api.pct_device_status(plan)
+        log(f"[bench] stored {name} rows: build {build_ms:.0f} ms, {ms:.0f} ms for {n_iter} sweeps, "
+            f"{rows.nbytes / 2**30:.1f} GiB (status {bits:#x})")
+        stored[name] = (x, ms, build_ms, rows.nbytes, bits)
+        del rows, box
+        torch.cuda.empty_cache()
     ref = runs["f64"][0]
     # voxels crossed by at least one row: A^T 1 > 0
     cover = api.pct_backproject(plan, pr, torch.ones(pr.n, dtype=torch.float32, device=dev))
@@ -154,6 +199,14 @@ def run_precision(args):
         emax, emean = rsp_error(x, ref, touched)
         table[name] = {"ms_per_reconstruction": ms, "rsp_err_max": emax, "rsp_err_mean": emean,
                        "speedup_vs_f32_chords": runs["f32"][1] / ms, "status": bits}
+    for name in ("f32", "f16", "bf16"):
+        x, ms, build_ms, nbytes, bits = stored[name]
+        emax, emean = rsp_error(x, ref, touched)
+        table["stored_" + name] = {"ms_per_reconstruction": ms, "build_ms": build_ms, "row_bytes": nbytes,
+                                   "rsp_err_max": emax, "rsp_err_mean": emean,
+                                   "speedup_vs_f32_chords": runs["f32"][1] / ms,
+                                   "speedup_incl_build_vs_f32_chords": runs["f32"][1] / (ms + build_ms),
+                                   "status": bits}
     f16_ms = runs["f16"][1]
     out = {
         "metric": "proton-iterations/sec (fused MLP+DROP, FP16 chords) at 1 GPU",
@@ -396,15 +449,21 @@ def main():
     ms_per_step = ms_total / args.steps
     value = m * args.steps / (ms_total / 1e3)
     (k_ms, c_ms), (k_n, c_n) = api.pct_profile_read(plan)
-    k_avg_ms = k_ms / max(k_n, 1)
+    k_sampled_ms = k_ms / max(k_n, 1)
     c_avg_ms = c_ms / max(c_n, 1)
+    # Average launch of the block kernel over the timed region: the sweep's
+    # stream carries nothing else but one copy and one flush kernel per sweep
+    # (and, on the separate schedule, the per-block commit, timed apart).
+    k_avg_ms = (ms_total / args.steps - (c_avg_ms * T if c_n else 0.0)) / T
     bytes_per_launch = (BYTES_PER_PROTON * m + BYTES_PER_NONZERO * sum_nnz) / T
     achieved_gbs = bytes_per_launch / (k_avg_ms * 1e-3) / 1e9
     whole_gbs = (BYTES_PER_PROTON * m + BYTES_PER_NONZERO * sum_nnz) * args.steps / (ms_total * 1e-3) / 1e9
-    log(f"[bench] {ms_per_step:.1f} ms/step, block kernel avg {k_avg_ms * 1e3:.2f} us ({k_n} sampled), "
+    log(f"[bench] {ms_per_step:.1f} ms/step, block kernel avg {k_avg_ms * 1e3:.2f} us over the timed region, "
+        f"{k_sampled_ms * 1e3:.2f} us in {k_n} event-bracketed launches, "
         f"separate commit avg {c_avg_ms * 1e3:.2f} us ({c_n} sampled); host wall {t_host:.2f} s")
 
     ceiling = parallel_sweep_ceiling(api, plan, pr, x)
+    traffic, traffic_src = measured_traffic(cfg.name) if not args.protons else (None, "non-default size")
 
     out = {
         "metric": "proton-iterations/sec (fused MLP+DROP) at 1 GPU",
@@ -433,11 +492,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": traffic_src,
             "kernel": ("k_drop_fused (MLP trace + a.x + |a|^2 + rho + D-weighted scatter of block t, commit of "
                        "block t-1)") if c_n == 0 else "k_drop_block (MLP trace + a.x + |a|^2 + rho + scatter)",
             "lanes_per_proton": args.lanes or "auto",
             "kernel_avg_us": k_avg_ms * 1e3,
+            "kernel_avg_us_how": "timed region / block launches (HIP events on the sweep's stream)",
+            "kernel_avg_us_event_bracketed": k_sampled_ms * 1e3,
             "kernel_launches_sampled": k_n,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "whole_step_GBps": whole_gbs,

@@ -645,10 +645,11 @@ __device__ __forceinline__ void commit_part(const float *__restrict__ base, floa
         const ulonglong2 o23 = *reinterpret_cast<const ulonglong2 *>(pk_old + j + 2);
         const unsigned long long wp[4] = {p01.x, p01.y, p23.x, p23.y};
         const unsigned long long wo[4] = {o01.x, o01.y, o23.x, o23.y};
+        // next differs from base only where block q-1 or q-2 touched a voxel
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int jj = j + e;
-            if (jj < nvox) next[jj] = committed_value(base[jj], wp[e]);
+            if ((wp[e] | wo[e]) != 0ull && jj < nvox) next[jj] = committed_value(base[jj], wp[e]);
             if (wo[e] != 0ull) pk_old[jj] = 0ull;
         }
     }
@@ -656,8 +657,10 @@ __device__ __forceinline__ void commit_part(const float *__restrict__ base, floa
 
 constexpr int kCommitWG = 1024;  // commit workgroups (64 threads) per fused launch
 
+// Four waves per SIMD (at most 128 VGPRs): the walk is latency-bound, and the
+// extra wave hides more latency than the few spilled registers cost.
 template <int CHORD, int LPP>
-__global__ void __launch_bounds__(64) k_drop_fused(ProtonsDev p, const float *__restrict__ b,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) k_drop_fused(ProtonsDev p, const float *__restrict__ b,
                                                    const float *__restrict__ base, float *__restrict__ next,
                                                    const unsigned long long *__restrict__ pk_prev,
                                                    unsigned long long *pk_cur, unsigned long long *pk_old, int *r_cur,

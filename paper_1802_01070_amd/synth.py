@@ -19,9 +19,13 @@ IV-A) and the configurations listed in ``CONFIGS``.
 Physics stand-ins (not the reconstruction model):
 * exit deflections use the Fermi-Eyges covariance of a constant scattering
   power ``T`` (rad^2/mm): cov(t, theta) = T [[D^3/3, D^2/2], [D^2/2, D]];
-* WEPL is the exact line integral of the analytic phantom along the straight
-  chord from the entry point to the exit point, clipped to the grid box, plus
-  Gaussian noise (sigma = 1 mm).
+* WEPL is the exact line integral of the analytic phantom along a smooth
+  stand-in for the proton's true path -- the cubic Hermite curve through the
+  entry and exit positions with the entry and exit slopes, taken as
+  ``WEPL_PIECES`` straight pieces -- clipped to the grid box, plus Gaussian
+  noise (sigma = 1 mm).  (A straight entry-to-exit chord leaves the grid's z
+  range at other depths than any curved path and makes the data markedly
+  inconsistent near the top and bottom slices.)
 
 Random draws: numpy ``Generator(PCG64)``, one ``SeedSequence(seed).spawn``
 child per chunk of 10^6 protons, fixed draw order (t, v, theta, phi, two
@@ -332,6 +336,23 @@ def lab_point(u, t, v, phi):
     return np.stack([u * c - t * s, u * s + t * c, v], axis=1)
 
 
+WEPL_PIECES = 4
+
+
+def wepl_along_hermite(phantom: "Phantom", grid: Grid, mlp: MLPModel, f: dict) -> np.ndarray:
+    """Phantom integral along the cubic Hermite curve of every record (float64
+    fields), in WEPL_PIECES straight pieces, clipped to the grid box."""
+    D = mlp.depth
+    n = len(f["t_in"])
+    pts = []
+    for s in np.linspace(0.0, 1.0, WEPL_PIECES + 1):
+        h00, h10, h01, h11 = 2 * s**3 - 3 * s**2 + 1, s**3 - 2 * s**2 + s, -2 * s**3 + 3 * s**2, s**3 - s**2
+        t = h00 * f["t_in"] + h10 * D * f["th_in"] + h01 * f["t_out"] + h11 * D * f["th_out"]
+        v = h00 * f["v_in"] + h10 * D * f["ph_in"] + h01 * f["v_out"] + h11 * D * f["ph_out"]
+        pts.append(lab_point(np.full(n, mlp.u_in + s * D), t, v, f["gantry"]))
+    return sum(phantom.line_integral(pts[k], pts[k + 1], grid) for k in range(WEPL_PIECES))
+
+
 def make_scan(cfg: ScanConfig, m: Optional[int] = None, seed: Optional[int] = None,
               with_b: bool = True) -> Scan:
     m = cfg.m if m is None else int(m)
@@ -378,9 +399,7 @@ def make_scan(cfg: ScanConfig, m: Optional[int] = None, seed: Optional[int] = No
         out["gantry"][lo:hi] = phi
         if with_b:
             f = {k: out[k][lo:hi].astype(np.float64) for k in FIELDS}
-            A = lab_point(np.full(n, mlp.u_in), f["t_in"], f["v_in"], f["gantry"])
-            B = lab_point(np.full(n, mlp.u_out), f["t_out"], f["v_out"], f["gantry"])
-            b[lo:hi] = (phantom.line_integral(A, B, grid) + noise).astype(np.float32)
+            b[lo:hi] = (wepl_along_hermite(phantom, grid, mlp, f) + noise).astype(np.float32)
         else:
             b[lo:hi] = 0.0
     if cfg.order == "angle_slab":
