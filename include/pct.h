@@ -117,6 +117,13 @@ typedef struct {
     int64_t n;                  /* number of protons, >= 0                        */
 } pct_protons;
 
+/* Writable SoA proton arrays of `capacity` records (device memory). */
+typedef struct {
+    float *t_in, *v_in, *th_in, *ph_in, *t_out, *v_out, *th_out, *ph_out, *gantry;
+    int64_t capacity;
+} pct_protons_buf;
+
+
 /* ---- plan --------------------------------------------------------------- */
 /* Host object holding the grid, the MLP model and its FP64 coefficient table
  * (one row per vertex: t_k = c0t t_in + c0th th_in + c2t t_out + c2th th_out).
@@ -208,6 +215,18 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
 int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
            void *ws, size_t ws_bytes, void *stream);
 
+/* Within-block ordering.  Writes the records (and b, if not NULL) to out with
+ * every block of `block` consecutive records sorted by (entry slice of v_in,
+ * t_in, input position).  The DROP block update is a sum over the rows of the
+ * block, so the order inside a block does not change it (with the FP32 value
+ * type the block accumulator is order-independent and results are bitwise
+ * equal); ordered blocks let the fused block kernel give each XCD a band of
+ * neighbouring paths whose voxels stay in that XCD's L2.  Needs 1 <= block <=
+ * 8192 and out->capacity >= p->n; out must not alias p.  Host-synchronous
+ * validation, asynchronous on `stream`. */
+int pct_order_blocks(const pct_plan *plan, const pct_protons *p, const float *b, int64_t block,
+                     const pct_protons_buf *out, float *b_out, void *stream);
+
 /* ---- stored rows (precision form) ----------------------------------------
  * The precision form lets the chord lengths be stored rather than recomputed.
  * With 288 GB of HBM the rows of the scans here fit (10^7 protons x ~257
@@ -253,12 +272,6 @@ int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const floa
  * v_out); every region is solved on its own (any entry point above, on a
  * region plan); each slice of the final image is taken from the region whose
  * core (non-overlapped part) holds it (selectSlice). */
-
-/* Writable SoA proton arrays of `capacity` records (device memory). */
-typedef struct {
-    float *t_in, *v_in, *th_in, *ph_in, *t_out, *v_out, *th_out, *ph_out, *gantry;
-    int64_t capacity;
-} pct_protons_buf;
 
 /* Host only.  Region r of n_regions: core slices [core_lo[r], core_hi[r]] =
  * [floor(r nz / R), floor((r+1) nz / R) - 1]; region slices [z_lo[r],

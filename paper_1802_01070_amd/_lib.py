@@ -26,7 +26,8 @@ EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan
            "pct_plan_upload", "pct_device_status", "pct_mlp_trace", "pct_forward", "pct_backproject",
            "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read",
            "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
-           "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows")
+           "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows",
+           "pct_order_blocks")
 
 
 class PctError(RuntimeError):
@@ -98,6 +99,7 @@ def lib() -> C.CDLL:
             "pct_select_slices": ([vp, vp, i32, vp, i32, i32, i32, i32, vp], C.c_int),
             "pct_slice_span_histogram": ([vp, P(pct_protons), vp, vp, sz, vp], C.c_int),
             "pct_rows_count": ([vp, P(pct_protons), vp, vp, sz, vp], C.c_int),
+            "pct_order_blocks": ([vp, P(pct_protons), vp, i64, P(pct_protons_buf), vp, vp], C.c_int),
             "pct_rows_build": ([vp, P(pct_protons), i32, vp, vp, vp, vp, vp, sz, vp], C.c_int),
             "pct_drop_iterate_rows": ([vp, P(pct_rows), vp, vp, P(pct_drop_opts), vp, sz, vp], C.c_int),
         }

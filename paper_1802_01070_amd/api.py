@@ -303,6 +303,20 @@ def pct_region_select(plan: Plan, p: Protons, b: Optional[torch.Tensor], z_lo: i
     return sub, (b_out[:n] if b_out is not None else None)
 
 
+def pct_order_blocks(plan: Plan, p: Protons, b: Optional[torch.Tensor], block: int):
+    """Copy of the records (and b) with every block of `block` consecutive
+    records ordered by (entry slice, t_in, input position): (Protons, b)."""
+    dev = plan.device
+    bufs = {k: torch.empty(p.n, dtype=torch.float32, device=dev) for k in FIELDS}
+    b_out = torch.empty(p.n, dtype=torch.float32, device=dev) if b is not None else None
+    out = _lib.make_protons_buf({k: v.data_ptr() for k, v in bufs.items()}, p.n)
+    bp = _dev(b, "b", dtype=torch.float32, numel=p.n) if b is not None else None
+    st = lib().pct_order_blocks(plan.handle, C.byref(p.s), bp, int(block), C.byref(out),
+                                C.c_void_p(b_out.data_ptr()) if b_out is not None else None, _stream(dev))
+    check(st, "pct_order_blocks")
+    return Protons(bufs, device=dev), b_out
+
+
 def pct_select_slices(plan: Plan, src: torch.Tensor, src_z0: int, dst: torch.Tensor, dst_z0: int, z_first: int,
                       z_count: int):
     code = _dtype_code(src)

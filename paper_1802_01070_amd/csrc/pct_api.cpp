@@ -430,6 +430,26 @@ int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const floa
                                        stream));
 }
 
+int pct_order_blocks(const pct_plan *plan, const pct_protons *p, const float *b, int64_t block,
+                     const pct_protons_buf *out, float *b_out, void *stream)
+{
+    if (!plan || !out) return PCT_ERR_INVALID_ARG;
+    int st = check_protons(p);
+    if (st) return st;
+    if (block <= 0 || block > 8192) return PCT_ERR_INVALID_ARG;
+    if (p->n == 0) return PCT_OK;
+    if (out->capacity < p->n) return PCT_ERR_INVALID_ARG;
+    float *ptrs[9] = {out->t_in, out->v_in, out->th_in, out->ph_in, out->t_out, out->v_out, out->th_out, out->ph_out,
+                      out->gantry};
+    for (float *q : ptrs)
+        if (!q) return PCT_ERR_INVALID_ARG;
+    if (b && !b_out) return PCT_ERR_INVALID_ARG;
+    if ((p->n + block - 1) / block >= (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
+    ProtonsBufDev o{out->t_in, out->v_in, out->th_in, out->ph_in, out->t_out, out->v_out, out->th_out, out->ph_out,
+                    out->gantry};
+    return hip_status(launch_order_blocks(*plan, protons_dev(p), p->n, b, block, o, b ? b_out : nullptr, stream));
+}
+
 int pct_region_layout(int32_t nz, int32_t n_regions, int32_t halo, int32_t *z_lo, int32_t *z_hi, int32_t *core_lo,
                       int32_t *core_hi)
 {

@@ -88,6 +88,8 @@ int launch_rows_build(const pct_plan &pl, const ProtonsDev &p, int64_t n, int ch
 int launch_drop_rows(pct_plan &pl, const pct_rows &rows, const float *b, float *x, const pct_drop_opts &o, void *ws,
                      void *stream);
 int launch_span_histogram(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *hist, void *stream);
+int launch_order_blocks(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, int64_t block,
+                        const ProtonsBufDev &out, float *b_out, void *stream);
 int copy_device(void *dst, const void *src, size_t bytes, void *stream);
 int launch_region_select(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, int z_lo, int z_hi,
                          const ProtonsBufDev &out, int64_t capacity, float *b_out, int64_t *count, void *ws,

@@ -656,6 +656,7 @@ __device__ __forceinline__ void commit_part(const float *__restrict__ base, floa
 }
 
 constexpr int kCommitWG = 1024;  // commit workgroups (64 threads) per fused launch
+static_assert(kCommitWG % 8 == 0, "proton workgroups must start on XCD 0");
 
 // Four waves per SIMD (at most 128 VGPRs): the walk is latency-bound, and the
 // extra wave hides more latency than the few spilled registers cost.
@@ -678,8 +679,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
     const int lane = threadIdx.x;
     const int grp = lane / LPP;
     const int l = lane % LPP;
-    const int64_t i = lo + int64_t(blockIdx.x - kCommitWG) * GPW + grp;
-    bool active = i < hi;
+    // XCD-aware placement: workgroup w runs on XCD w mod 8, so the proton
+    // workgroups are dealt to the eight XCDs in contiguous runs of the block
+    // (8 * per_xcd workgroups are launched; the padding ones idle).  With the
+    // block ordered by entry slice and lateral position, each XCD then walks
+    // a band of neighbouring paths and finds their voxels in its own L2.
+    const int wq = int(blockIdx.x) - kCommitWG;
+    const int64_t n_wg = (hi - lo + GPW - 1) / GPW;
+    const int64_t per_xcd = (n_wg + 7) / 8;
+    const int64_t wg = int64_t(wq % 8) * per_xcd + wq / 8;
+    const int64_t i = lo + wg * GPW + grp;
+    bool active = wg < n_wg && i < hi;
     Rec r{};
     double bi = 0.0;
     if (active) {
@@ -1282,6 +1292,60 @@ __global__ void __launch_bounds__(64) k_drop_rows_fused(RowsDev rows, const floa
 }
 
 // ---------------------------------------------------------------------------
+// within-block ordering: every block of consecutive records is sorted by
+// (entry slice, t_in, input position) with a bitonic sort of packed 64-bit
+// keys in LDS, one workgroup per block
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long order_key(const ProtonsDev &p, int64_t i, int local, const GridDev &g)
+{
+    const unsigned slice = unsigned(slice_index(p.v_in[i], g) + 1);  // 0 for a non-finite v_in
+    unsigned t = __float_as_uint(p.t_in[i]);
+    t ^= (t & 0x80000000u) ? 0xFFFFFFFFu : 0x80000000u;               // order-preserving bits
+    return (static_cast<unsigned long long>(slice & 0xFFFFu) << 48) | (static_cast<unsigned long long>(t) << 16) |
+           static_cast<unsigned long long>(local);
+}
+
+__global__ void __launch_bounds__(kSelWG) k_order_blocks(ProtonsDev p, const float *b, int64_t n, int64_t block,
+                                                          int p2, GridDev g, ProtonsBufDev out, float *b_out)
+{
+    extern __shared__ unsigned long long keys[];
+    const int64_t lo = int64_t(blockIdx.x) * block;
+    const int cnt = int(min(block, n - lo));
+    for (int q = threadIdx.x; q < p2; q += kSelWG) keys[q] = q < cnt ? order_key(p, lo + q, q, g) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int q = threadIdx.x; q < p2; q += kSelWG) {
+                const int r = q ^ j;
+                if (r > q) {
+                    const unsigned long long a = keys[q], c = keys[r];
+                    const bool up = (q & k) == 0;
+                    if ((a > c) == up) {
+                        keys[q] = c;
+                        keys[r] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = threadIdx.x; q < cnt; q += kSelWG) {
+        const int64_t src = lo + int64_t(keys[q] & 0xFFFFull);
+        const int64_t dst = lo + q;
+        out.t_in[dst] = p.t_in[src];
+        out.v_in[dst] = p.v_in[src];
+        out.th_in[dst] = p.th_in[src];
+        out.ph_in[dst] = p.ph_in[src];
+        out.t_out[dst] = p.t_out[src];
+        out.v_out[dst] = p.v_out[src];
+        out.th_out[dst] = p.th_out[src];
+        out.ph_out[dst] = p.ph_out[src];
+        out.gantry[dst] = p.gantry[src];
+        if (b_out) b_out[dst] = b[src];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline char *wsb(void *ws) { return static_cast<char *>(ws); }
@@ -1461,7 +1525,8 @@ static void launch_fused(int lanes, hipStream_t s, const ProtonsDev &p, const fl
     switch (lanes) {
 #define PCT_LAUNCH_FUSED(LPP)                                                                                    \
     case LPP: {                                                                                                  \
-        const unsigned grid = unsigned(kCommitWG + (n + (64 / LPP) - 1) / (64 / LPP));                        \
+        const int64_t n_wg = (n + (64 / LPP) - 1) / (64 / LPP);                                              \
+        const unsigned grid = unsigned(kCommitWG + 8 * ((n_wg + 7) / 8));                                    \
         const size_t lds = size_t(64 / LPP) * 3 * size_t(K + 1) * sizeof(double) + stash_bytes<float>();      \
         hipLaunchKernelGGL((k_drop_fused<CHORD, LPP>), dim3(grid), dim3(64), lds, s, p, b, base, next, pk_prev,  \
                            pk_cur, pk_old, r_cur, r_prev, r_old, r_reset, tab, K, g, lo, hi, lambda, status,     \
@@ -1722,6 +1787,18 @@ int launch_span_histogram(const pct_plan &pl, const ProtonsDev &p, int64_t n, in
     const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(2048, (n + kSelWG - 1) / kSelWG)));
     hipLaunchKernelGGL(k_span_histogram, dim3(grid), dim3(kSelWG), size_t(pl.grid.nz) * sizeof(unsigned), s, p, n, g,
                        reinterpret_cast<unsigned long long *>(hist));
+    return hipGetLastError();
+}
+
+int launch_order_blocks(const pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, int64_t block,
+                        const ProtonsBufDev &out, float *b_out, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int p2 = 2;
+    while (p2 < block && p2 < n) p2 <<= 1;
+    const int64_t nb = (n + block - 1) / block;
+    hipLaunchKernelGGL(k_order_blocks, dim3(unsigned(nb)), dim3(kSelWG), size_t(p2) * sizeof(unsigned long long), s, p,
+                       b, n, block, p2, grid_dev(pl.grid), out, b_out);
     return hipGetLastError();
 }
 

@@ -266,6 +266,26 @@ def test_stored_row_calls_validate(plan):
     assert run(plan, C.byref(rows), None, v, C.byref(ok), FAKE_WS, nb, None) == -1
 
 
+def test_order_blocks_validates(plan):
+    L = _lib.lib()
+    p = fake_protons(100)
+    buf = _lib.make_protons_buf({k: 0x9000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, 100)
+    small = _lib.make_protons_buf({k: 0x9000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, 99)
+    v = C.c_void_p(0xA000)
+    assert L.pct_order_blocks(plan, C.byref(p), None, 0, C.byref(buf), None, None) == -1
+    assert L.pct_order_blocks(plan, C.byref(p), None, 8193, C.byref(buf), None, None) == -1
+    assert L.pct_order_blocks(plan, C.byref(p), None, 64, C.byref(small), None, None) == -1
+    assert L.pct_order_blocks(plan, C.byref(p), v, 64, C.byref(buf), None, None) == -1     # b without b_out
+    assert L.pct_order_blocks(plan, C.byref(p), None, 64, None, None, None) == -1
+
+
+def test_header_compiles_as_c():
+    import subprocess
+    r = subprocess.run(["gcc", "-fsyntax-only", "-std=c11", "-Wall", "-Werror", "-x", "c",
+                        os.path.join(ROOT, "include", "pct.h")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_status_strings():
     for st in range(-7, 1):
         s = _lib.status_string(st)

@@ -508,6 +508,39 @@ def test_fused_commit_is_bitwise_the_separate_schedule():
     assert_status_clean(plan)
 
 
+def test_order_blocks_sorted_permutation_and_drop_unchanged():
+    # within-block ordering is a per-block permutation sorted by (entry
+    # slice, t_in, input position); DROP's block update is a sum over the
+    # block's rows, so the FP32 result (order-independent accumulator) must be
+    # bitwise the same on the ordered copy, also on a ragged last block
+    c = synth.CONFIGS[2]
+    sc = scan(2, 64100)
+    plan, pr = gpu_setup(sc)
+    b = torch.from_numpy(sc.b).to(DEV)
+    op, ob = api.pct_order_blocks(plan, pr, b, c.block)
+    g = sc.grid
+    v = sc.protons["v_in"].astype(np.float64)
+    sl = np.clip(np.floor((v - g.origin[2]) / g.pitch[2]), 0, g.nz - 1)
+    t = sc.protons["t_in"]
+    perm = []
+    for lo in range(0, sc.m, c.block):
+        idx = np.arange(lo, min(sc.m, lo + c.block))
+        perm.append(idx[np.lexsort((idx, t[idx], sl[idx]))])
+    perm = np.concatenate(perm)
+    for k in ("t_in", "v_in", "th_out", "gantry"):
+        assert np.array_equal(op.t[k].cpu().numpy(), sc.protons[k][perm]), k
+    assert np.array_equal(ob.cpu().numpy(), sc.b[perm])
+    x0 = torch.from_numpy(np.random.default_rng(8).uniform(0.9, 1.1, g.nvox).astype(np.float32)).to(DEV)
+    for lanes in (0, 32):
+        xa = x0.clone()
+        api.pct_drop_iterate(plan, pr, b, xa, block=c.block, lam=c.lam, n_iter=2, lanes=lanes)
+        xb = x0.clone()
+        api.pct_drop_iterate(plan, op, ob, xb, block=c.block, lam=c.lam, n_iter=2, lanes=lanes)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xb), lanes
+    assert_status_clean(plan)
+
+
 # ---------------------------------------------------------------------------
 # differentiation form: gradient checks and the gradient-descent driver
 # ---------------------------------------------------------------------------
