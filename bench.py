@@ -21,6 +21,9 @@ Two more workloads, each printing its own JSON line:
     --config 5   differentiation form: 2*10^7 protons on the 256x256x64 scan,
                  20 steps of TV-regularised gradient descent (forward +
                  backward projection per step); loss curve and pass rates.
+    --config bsweep  block-size variants on the 10^7-proton 200x200x32 scan
+                 (B = 3200, 32000, 320000): time per sweep and insert RSP
+                 error after each of 4 sweeps.
     --config alg1  the multi-region split (Algorithm 1) of the 10^7-proton
                  200x200x32 scan into two overlapping z regions, run one after
                  the other on this GPU, against the single-volume solve: insert
@@ -153,6 +156,7 @@ def run_precision(args):
     from paper_1802_01070_amd import api, synth
     cfg = synth.CONFIGS[4]
     m = args.protons or cfg.m
+    log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
     sc = synth.make_scan(cfg, m=m)
     log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
@@ -232,6 +236,7 @@ def run_gradient(args):
     from paper_1802_01070_amd import api, synth
     cfg = synth.CONFIGS[5]
     m = args.protons or cfg.m
+    log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
     sc = synth.make_scan(cfg, m=m)
     log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
@@ -300,6 +305,49 @@ def insert_errors(sc, x):
     return out
 
 
+def run_block_sizes(args):
+    """Block-size variants of the plain method on the 10^7-proton scan."""
+    import torch
+    from paper_1802_01070_amd import api, synth
+    cfg = synth.CONFIGS[2]
+    m = args.protons or cfg.m
+    log(f"[bench] generating {cfg.name}: {m} protons")
+    t0 = time.perf_counter()
+    sc = synth.make_scan(cfg, m=m)
+    log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
+    dev = "cuda:0"
+    plan = api.Plan(sc.grid, sc.mlp, dev)
+    pr0 = api.Protons(sc.protons, dev)
+    b0 = torch.from_numpy(sc.b).to(dev)
+    n_sweeps = 4
+    variants = []
+    for B in (3200, 32000, 320000):
+        pr, b = api.pct_order_blocks(plan, pr0, b0, min(B, 8192)) if B <= 8192 else (pr0, b0)
+        x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
+        api.pct_drop_iterate(plan, pr, b, x, block=B, lam=cfg.lam, n_iter=1)       # warm-up (records the graph)
+        x.fill_(1.0)
+        sweeps = []
+        for k in range(n_sweeps):
+            ms = time_events(lambda: api.pct_drop_iterate(plan, pr, b, x, block=B, lam=cfg.lam, n_iter=1))
+            sweeps.append({"sweep": k + 1, "ms": ms, "inserts": insert_errors(sc, x)})
+        bits = api.pct_device_status(plan)
+        log(f"[bench] B={B}: {[round(s['ms'], 1) for s in sweeps]} ms per sweep, status {bits:#x}")
+        variants.append({"block": B, "blocks_per_sweep": (m + B - 1) // B, "sweeps": sweeps, "status": bits})
+    best = min(variants, key=lambda v: np.mean([s["ms"] for s in v["sweeps"]]))
+    ms = float(np.mean([s["ms"] for s in best["sweeps"]]))
+    out = {
+        "metric": "proton-iterations/sec (fused MLP+DROP, block-size variants) at 1 GPU",
+        "value": m / (ms * 1e-3), "unit": "proton-iterations/s", "n_gpus": 1, "steps": n_sweeps, "warmup": 1,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {sc.grid.nx}x{sc.grid.ny}x{sc.grid.nz} grid, {m} protons, "
+                               f"lambda {cfg.lam}, DROP block 3200 / 32000 / 320000 (value: the fastest, "
+                               f"B={best['block']})"},
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_regions(args):
     """Algorithm 1 on the 10^7-proton 200x200x32 scan against the single-volume
     solve, sweep by sweep."""
@@ -308,6 +356,7 @@ def run_regions(args):
     cfg = synth.CONFIGS[2]
     m = args.protons or cfg.m
     n_sweeps = args.steps if args.steps != 12 else 6
+    log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
     sc = synth.make_scan(cfg, m=m)
     log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
@@ -400,9 +449,12 @@ def main():
         return run_gradient(args)
     if args.config == "alg1":
         return run_regions(args)
+    if args.config == "bsweep":
+        return run_block_sizes(args)
     key = int(args.config) if args.config.isdigit() else args.config
     cfg = synth.CONFIGS[key]
     m = args.protons or cfg.m
+    log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
     sc = synth.make_scan(cfg, m=m)
     log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")

@@ -35,6 +35,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -370,11 +371,12 @@ def make_scan(cfg: ScanConfig, m: Optional[int] = None, seed: Optional[int] = No
     b = np.empty(m, np.float32)
     n_chunks = max(1, (m + CHUNK - 1) // CHUNK)
     children = np.random.SeedSequence(seed).spawn(n_chunks)
-    for c in range(n_chunks):
+
+    def chunk(c):
         lo, hi = c * CHUNK, min(m, (c + 1) * CHUNK)
         n = hi - lo
         if n <= 0:
-            break
+            return
         rng = np.random.Generator(np.random.PCG64(children[c]))
         t_in = rng.uniform(-cfg.r_hull, cfg.r_hull, n)
         v_in = rng.uniform(zlo, zhi, n)
@@ -383,12 +385,12 @@ def make_scan(cfg: ScanConfig, m: Optional[int] = None, seed: Optional[int] = No
         zt = rng.standard_normal((n, 2))
         zv = rng.standard_normal((n, 2))
         noise = rng.standard_normal(n) * cfg.noise_mm
-        dt = zt @ chol.T
-        dv = zv @ chol.T
-        t_out = t_in + th_in * D + dt[:, 0]
-        th_out = th_in + dt[:, 1]
-        v_out = v_in + ph_in * D + dv[:, 0]
-        ph_out = ph_in + dv[:, 1]
+        # correlated deflections chol @ z, written out (no BLAS call: results
+        # must not depend on how a library splits work across threads)
+        t_out = t_in + th_in * D + (chol[0, 0] * zt[:, 0] + chol[0, 1] * zt[:, 1])
+        th_out = th_in + (chol[1, 0] * zt[:, 0] + chol[1, 1] * zt[:, 1])
+        v_out = v_in + ph_in * D + (chol[0, 0] * zv[:, 0] + chol[0, 1] * zv[:, 1])
+        ph_out = ph_in + (chol[1, 0] * zv[:, 0] + chol[1, 1] * zv[:, 1])
         idx = np.arange(lo, hi, dtype=np.int64)
         ang = (idx * cfg.n_angles) // m
         phi = (2.0 * np.pi * ang / cfg.n_angles).astype(np.float32)
@@ -402,6 +404,15 @@ def make_scan(cfg: ScanConfig, m: Optional[int] = None, seed: Optional[int] = No
             b[lo:hi] = (wepl_along_hermite(phantom, grid, mlp, f) + noise).astype(np.float32)
         else:
             b[lo:hi] = 0.0
+
+    # chunks are independent (own seed, disjoint output ranges); numpy
+    # releases the GIL inside its array operations, so threads overlap them
+    if n_chunks > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(8, n_chunks, os.cpu_count() or 1)) as ex:
+            list(ex.map(chunk, range(n_chunks)))
+    else:
+        chunk(0)
     if cfg.order == "angle_slab":
         ang = np.floor(out["gantry"].astype(np.float64) * cfg.n_angles / (2 * np.pi) + 0.5).astype(np.int64)
         slab = np.floor((out["v_in"].astype(np.float64) - zlo) / cfg.slab_mm).astype(np.int64)

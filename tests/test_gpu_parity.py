@@ -334,6 +334,37 @@ def test_drop_full_size_sampled_blocks():
     assert_status_clean(plan)
 
 
+def test_drop_full_size_head_scan_sampled_blocks():
+    # the 5*10^7-proton 256x256x64 head scan (sorted by angle, slab, t_in;
+    # block 6400) at full size, ordered inside blocks as the benchmark runs
+    # it; sampled blocks checked against the oracle from the GPU's iterate
+    c = synth.CONFIGS[3]
+    say(f"DROP cfg3 full-size sampled blocks: generating {c.m} protons")
+    sc = scan(3, c.m)
+    plan, pr = gpu_setup(sc)
+    b = torch.from_numpy(sc.b).to(DEV)
+    pr, b = api.pct_order_blocks(plan, pr, b, c.block)
+    ob = b.cpu().numpy()
+    op = {k: v.cpu().numpy() for k, v in pr.t.items()}
+    x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+    T = (sc.m + c.block - 1) // c.block
+    done = 0
+    for t in (0, 1, T // 2, T - 1):
+        if t > done:
+            api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_begin=done, block_end=t)
+        x_before = x.double().cpu().numpy()
+        api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_begin=t, block_end=t + 1)
+        lo, hi = t * c.block, min(sc.m, (t + 1) * c.block)
+        ref = oracle.drop(sc.grid, sc.mlp, {k: v[lo:hi] for k, v in op.items()}, ob[lo:hi], x_before,
+                          block=c.block, lam=c.lam, n_iter=1)
+        err = rsp_close(x.double().cpu().numpy(), ref, 0)
+        say(f"  block {t}: max err {err:.3e}")
+        assert err <= 1e-5
+        done = t + 1
+    assert_status_clean(plan)
+    _scans.pop((3, c.m, None), None)
+
+
 def test_drop_steep_paths_use_single_lane_fallback():
     # slopes of 3 at a 30 degree gantry angle make the path non-monotone along
     # its dominant axis; the block kernel must fall back to one lane per row
