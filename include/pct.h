@@ -171,8 +171,17 @@ typedef struct {
  * schedule).  This flag asks for the separate schedule: one block kernel and
  * one commit kernel per block. */
 #define PCT_DROP_SEPARATE_COMMIT 0x8u
+/* FP32 value type, 64 lanes per proton, workspace sized for the block (see
+ * pct_workspace_size): by default the rows of block t+1 are traced in the
+ * launch that runs the DROP step of block t (the rows do not depend on x), so
+ * each block step no longer waits for its own walk; results are bitwise those
+ * of the other schedules.  This flag asks for the plain fused schedule. */
+#define PCT_DROP_NO_TRACE_AHEAD 0x10u
 
-/* Workspace bytes for problems of this plan (n protons, x of type dtype). */
+/* Workspace bytes for this plan and x of type dtype.  n > 0 adds two row
+ * slots for DROP blocks of up to n protons, which the traced-ahead schedule
+ * needs (2 * n * 6.4 KB); with n = 0 pct_drop_iterate uses the other
+ * schedules. */
 int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes);
 
 /* Writes the coefficient table into the workspace and clears its counters and

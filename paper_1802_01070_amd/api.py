@@ -40,9 +40,10 @@ def _dev(t: torch.Tensor, what: str, dtype=None, numel: Optional[int] = None):
 
 
 class Plan:
-    """A pct_plan plus its device workspace (uploaded once)."""
+    """A pct_plan plus its device workspace (uploaded once).  n_hint: the
+    largest DROP block that runs with the traced-ahead schedule."""
 
-    def __init__(self, grid, mlp, device="cuda:0", n_hint: int = 0, _handle: Optional[C.c_void_p] = None):
+    def __init__(self, grid, mlp, device="cuda:0", n_hint: int = 8192, _handle: Optional[C.c_void_p] = None):
         self.grid = grid
         self.mlp = mlp
         self.device = torch.device(device)

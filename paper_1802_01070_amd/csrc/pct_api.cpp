@@ -267,7 +267,7 @@ int pct_plan_table(const pct_plan *plan, double *tab, int64_t tab_len)
 int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes)
 {
     if (!plan || !bytes || n < 0 || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
-    *bytes = layout_for(plan->nvox, plan->K, dtype).total;
+    *bytes = layout_for(plan->nvox, plan->K, dtype).total + (n > 0 ? 2 * slot_bytes(n) : 0);
     return PCT_OK;
 }
 
@@ -350,7 +350,8 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (p->n > 0 && !b) return PCT_ERR_INVALID_ARG;
     if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
     if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
-    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT))
+    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT |
+                     PCT_DROP_NO_TRACE_AHEAD))
         return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
     if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 20)) return PCT_ERR_INVALID_ARG;
@@ -365,7 +366,8 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->n_iter == 0 || o->block_begin == end) return PCT_OK;
     pct_drop_opts oo = *o;
     oo.block_end = end;
-    return hip_status(launch_drop(*const_cast<pct_plan *>(plan), protons_dev(p), p->n, b, x, oo, ws, stream));
+    return hip_status(
+        launch_drop(*const_cast<pct_plan *>(plan), protons_dev(p), p->n, b, x, oo, ws, ws_bytes, stream));
 }
 
 int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,

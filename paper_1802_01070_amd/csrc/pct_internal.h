@@ -40,9 +40,14 @@ struct Layout {
     size_t cnt;      // nvox int32
     size_t x1;       // second copy of the iterate, nvox doubles
     size_t partial;  // kMaxPartials doubles
-    size_t total;
+    size_t total;    // end of the fixed part; the traced-ahead row slots follow
+
 };
 constexpr int kMaxPartials = 4096;
+// One traced-ahead row record: 12 stash entries x 64 lanes of (voxel, chord),
+// 64 lane counts and ||a_i||^2 (two slots of B records follow Layout::total).
+constexpr size_t kSlotRecordBytes = size_t(12) * 64 * 8 + 64 * 4 + 8;
+inline size_t slot_bytes(int64_t records) { return (size_t(records) * kSlotRecordBytes + 255) & ~size_t(255); }
 
 // header words (int32 index): status word, then the [jmin, jmax] voxel range
 // touched by a block, double-buffered by block parity (FP64 path), and four
@@ -81,7 +86,7 @@ int launch_forward(const pct_plan &pl, const ProtonsDev &p, int64_t n, const voi
 int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const void *r, int dtype, void *g,
                        void *ws, void *stream);
 int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x,
-                const pct_drop_opts &o, void *ws, void *stream);
+                const pct_drop_opts &o, void *ws, size_t ws_bytes, void *stream);
 int launch_rows_count(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *offsets, void *ws, void *stream);
 int launch_rows_build(const pct_plan &pl, const ProtonsDev &p, int64_t n, int chord_type, const int64_t *offsets,
                       int32_t *vox, void *chord, double *n2, void *ws, void *stream);

@@ -768,6 +768,194 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
     publish_range(jmin, jmax, r_cur);
 }
 
+// ---------------------------------------------------------------------------
+// Traced-ahead schedule (FP32, 64 lanes per proton).  The rows do not depend
+// on x, so launch q traces the rows of block q+1 while it runs the DROP
+// update of block q from the rows traced in launch q-1 (and commits block
+// q-1 as in k_drop_fused): the walk leaves the chain of dependent block
+// steps.  A row record holds the image of the lane stash (kStash entries x
+// 64 lanes, entry-major), the lane piece counts and ||a_i||^2; a lane whose
+// count exceeds kStash walks its slabs again in the DROP step, exactly as in
+// k_drop_fused, so both schedules give bitwise the same result.
+// ---------------------------------------------------------------------------
+struct SlotDev {
+    int *vox;      // [record][kStash][64]
+    float *chord;  // [record][kStash][64]
+    int *cnt;      // [record][64]
+    double *n2;    // [record]
+};
+
+static_assert(kSlotRecordBytes == size_t(kStash) * 64 * (sizeof(int) + sizeof(float)) + 64 * sizeof(int) +
+                                      sizeof(double),
+              "row record layout");
+
+__host__ __device__ inline SlotDev slot_at(char *base, int64_t records)
+{
+    SlotDev d;
+    d.vox = reinterpret_cast<int *>(base);
+    d.chord = reinterpret_cast<float *>(base + size_t(records) * kStash * 64 * sizeof(int));
+    d.cnt = reinterpret_cast<int *>(base + size_t(records) * kStash * 64 * (sizeof(int) + sizeof(float)));
+    d.n2 = reinterpret_cast<double *>(base + size_t(records) * (kStash * 64 * (sizeof(int) + sizeof(float)) +
+                                                                64 * sizeof(int)));
+    return d;
+}
+
+// Trace of record r of the block [wlo, whi) into slot wr (one proton per
+// one-wave workgroup).
+template <int CHORD>
+__device__ __forceinline__ void trace_role(const ProtonsDev &p, const SlotDev &wr, const double *__restrict__ tab,
+                                           int K, const GridDev &g, int64_t wlo, int64_t whi, int64_t r, double *P,
+                                           int *sj, float *sc, unsigned *status)
+{
+    const int lane = threadIdx.x;
+    const int64_t i = wlo + r;
+    if (i >= whi) return;  // uniform: one proton per workgroup
+    Rec rec = load_rec(p, i);
+    bool active = true;
+    if (!rec_finite(rec)) {
+        if (lane == 0) raise_status(status, PCT_DEV_NONFINITE);
+        active = false;
+        rec.cs = 1.0;
+        rec.sn = 0.0;
+    }
+    const GroupPath gp = stage_path<64>(rec, tab, K, g, P, lane, active);
+    StashSink<float, kStash> st{sj, sc, lane, {}, 0.0, 0};
+    st.re.init(rec);
+    {
+        Merge<StashSink<float, kStash>, CHORD> m(st, g);
+        walk_lane<64>(gp, lane, K, g, P, m);
+        m.finish();
+    }
+    if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
+    const double n2 = group_sum<64>(st.n2);
+    const int ns = min(st.count, kStash);
+    for (int k = 0; k < ns; ++k) {
+        const int64_t q = (r * kStash + k) * 64 + lane;
+        wr.vox[q] = sj[k * 64 + lane];
+        wr.chord[q] = sc[k * 64 + lane];
+    }
+    wr.cnt[r * 64 + lane] = active ? st.count : 0;
+    if (lane == 0) wr.n2[r] = active ? n2 : 0.0;
+}
+
+template <int CHORD>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_drop_pipe(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ base, float *__restrict__ next,
+            const unsigned long long *__restrict__ pk_prev, unsigned long long *pk_cur, unsigned long long *pk_old,
+            int *r_cur, const int *r_prev, const int *r_old, int *r_reset, SlotDev rd, SlotDev wr,
+            const double *__restrict__ tab, int K, GridDev g, int64_t lo, int64_t hi, int64_t wlo, int64_t whi,
+            int n_commit, double lambda, unsigned *status, int nvox)
+{
+    const int bid = int(blockIdx.x);
+    if (bid < n_commit) {
+        commit_part(base, next, pk_prev, pk_old, r_prev, r_old, r_reset, nvox, bid, n_commit);
+        return;
+    }
+    extern __shared__ double lds[];
+    double *P = lds;
+    char *stash = reinterpret_cast<char *>(lds + 3 * (K + 1));
+    int *sj = reinterpret_cast<int *>(stash);
+    float *sc = reinterpret_cast<float *>(stash + size_t(64) * kStash * sizeof(int));
+    const int lane = threadIdx.x;
+    // workgroups: [commit | trace of block q+1 | DROP step of block q]; the
+    // trace, the longer chain, is dispatched first
+    const int64_t n_d = hi - lo;
+    const int64_t per_xcd = (n_d + 7) / 8;
+    const int64_t n_w8 = 8 * ((whi - wlo + 7) / 8);  // keeps the DROP workgroups XCD-aligned
+    if (bid - n_commit < n_w8) {
+        trace_role<CHORD>(p, wr, tab, K, g, wlo, whi, int64_t(bid - n_commit), P, sj, sc, status);
+        return;
+    }
+    const int wq = int(bid - n_commit - n_w8);
+    {
+        // ---- DROP step of block q from its traced rows (XCD-aware placement)
+        const int64_t r = int64_t(wq % 8) * per_xcd + wq / 8;
+        bool active = r < n_d;
+        const int64_t i = lo + r;
+        double bi = 0.0, n2 = 0.0;
+        int cnt = 0;
+        if (active) {
+            bi = double(b[i]);
+            n2 = rd.n2[r];
+            cnt = rd.cnt[r * 64 + lane];
+            if (!isfinite(bi)) {
+                if (lane == 0) raise_status(status, PCT_DEV_NONFINITE);
+                active = false;
+            }
+        }
+        const bool spill = cnt > kStash;
+        const bool any_spill = group_any<64>(spill);
+        const LazyX xa{base, pk_prev};
+        int jr[kStash];
+        float cr[kStash];
+        double dot = 0.0;
+#pragma unroll
+        for (int k = 0; k < kStash; ++k) {
+            jr[k] = 0;
+            cr[k] = 0.f;
+            if (!spill && k < cnt) {
+                const int64_t q = (r * kStash + k) * 64 + lane;
+                jr[k] = rd.vox[q];
+                cr[k] = rd.chord[q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kStash; ++k)
+            if (!spill && k < cnt) dot += double(cr[k]) * xa(jr[k] & 0x7FFFFFFF);
+        Rec rec{};
+        GroupPath gp{};
+        if (any_spill) {
+            // lanes beyond the stash walk their slabs again (rare)
+            if (active) rec = load_rec(p, i);
+            if (!active) rec.cs = 1.0, rec.sn = 0.0;
+            gp = stage_path<64>(rec, tab, K, g, P, lane, active);
+            if (spill) {
+                DotSink<float, LazyX> ds;
+                ds.x = xa;
+                ds.dot = 0.0;
+                ds.n2 = 0.0;
+                ds.re.init(rec);
+                Merge<DotSink<float, LazyX>, CHORD> m(ds, g);
+                walk_lane<64>(gp, lane, K, g, P, m);
+                m.finish();
+                dot = ds.dot;
+            }
+        }
+        dot = group_sum<64>(dot);
+        int jmin = INT_MAX, jmax = -1;
+        if (active && n2 > 0.0) {
+            const double rho = lambda * (bi - dot) / n2;
+            if (!spill) {
+#pragma unroll
+                for (int k = 0; k < kStash; ++k) {
+                    if (k < cnt) {
+                        const int e = jr[k];
+                        const int j = e & 0x7FFFFFFF;
+                        atomicAdd(pk_cur + j, pack_contribution(rho * double(cr[k]), e < 0, status));
+                        jmin = min(jmin, j);
+                        jmax = max(jmax, j);
+                    }
+                }
+            } else {
+                DropScatterSink<float> sc2;
+                sc2.acc = pk_cur;
+                sc2.cnt = nullptr;
+                sc2.status = status;
+                sc2.rho = rho;
+                sc2.jmin = INT_MAX;
+                sc2.jmax = -1;
+                sc2.re.init(rec);
+                Merge<DropScatterSink<float>, CHORD> m(sc2, g);
+                walk_lane<64>(gp, lane, K, g, P, m);
+                m.finish();
+                jmin = sc2.jmin;
+                jmax = sc2.jmax;
+            }
+        }
+        publish_range(jmin, jmax, r_cur);
+    }
+}
+
 // Start of a fused sweep: X1 = x, all range slots empty.
 __global__ void __launch_bounds__(256) k_sweep_begin(const float *__restrict__ x, float *__restrict__ x1, int *slots,
                                                      int nvox)
@@ -1687,7 +1875,7 @@ static inline uint64_t bits_of(double v)
 
 template <typename T, int CHORD>
 static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
-                     const pct_drop_opts &o, void *ws, hipStream_t s)
+                     const pct_drop_opts &o, void *ws, size_t ws_bytes, hipStream_t s)
 {
     const bool prof = (o.flags & PCT_DROP_PROFILE) != 0;
     if (prof) {
@@ -1732,8 +1920,45 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         }
     };
     const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT);
+    const bool pipe = fused && lanes == 64 && !(o.flags & PCT_DROP_NO_TRACE_AHEAD) &&
+                      ws_bytes >= L.total + 2 * slot_bytes(o.block);
     auto sweep = [&](hipStream_t s, bool record_events) {
         if constexpr (sizeof(T) == 4) {
+            if (pipe) {
+                const FusedBufs F = fused_bufs(pl, ws, x);
+                SlotDev slot[2] = {slot_at(wsb(ws) + L.total, o.block),
+                                   slot_at(wsb(ws) + L.total + slot_bytes(o.block), o.block)};
+                const size_t lds = 3 * size_t(pl.K + 1) * sizeof(double) + stash_bytes<float>();
+                auto block_range = [&](int64_t t, int64_t &a, int64_t &e) {
+                    a = e = 0;
+                    if (t < o.block_end) {
+                        a = t * o.block;
+                        e = std::min<int64_t>(n, a + o.block);
+                    }
+                };
+                enqueue_fused(pl, F, o.block_begin, o.block_end, o.block, n, s, record_events, every,
+                              [&](hipStream_t s, int64_t q, int64_t lo, int64_t hi, const FusedStep &f) {
+                                  int64_t wlo, whi;
+                                  if (q == 0) {  // prologue: trace the first block
+                                      block_range(o.block_begin, wlo, whi);
+                                      hipLaunchKernelGGL((k_drop_pipe<CHORD>), dim3(unsigned(8 * ((whi - wlo + 7) / 8))),
+                                                         dim3(64),
+                                                         lds, s, p, b, f.base, f.next, f.pk_prev, f.pk_cur,
+                                                         f.pk_old, f.r_cur, f.r_prev, f.r_old, f.r_reset, slot[1],
+                                                         slot[0], tab, pl.K, g, int64_t(0), int64_t(0), wlo, whi, 0,
+                                                         o.lambda, status, F.nv);
+                                  }
+                                  block_range(o.block_begin + q + 1, wlo, whi);
+                                  const int64_t n_d = hi - lo;
+                                  const unsigned grid =
+                                      unsigned(kCommitWG + 8 * ((whi - wlo + 7) / 8) + 8 * ((n_d + 7) / 8));
+                                  hipLaunchKernelGGL((k_drop_pipe<CHORD>), dim3(grid), dim3(64), lds, s, p, b, f.base,
+                                                     f.next, f.pk_prev, f.pk_cur, f.pk_old, f.r_cur, f.r_prev,
+                                                     f.r_old, f.r_reset, slot[q % 2], slot[(q + 1) % 2], tab, pl.K,
+                                                     g, lo, hi, wlo, whi, kCommitWG, o.lambda, status, F.nv);
+                              });
+                return;
+            }
             if (fused) {
                 const FusedBufs F = fused_bufs(pl, ws, x);
                 enqueue_fused(pl, F, o.block_begin, o.block_end, o.block, n, s, record_events, every,
@@ -1756,28 +1981,30 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         reinterpret_cast<uint64_t>(p.gantry), reinterpret_cast<uint64_t>(b),
         reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
         uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
-        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), uint64_t(fused), bits_of(o.lambda), 0};
+        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), uint64_t(fused) + 2 * uint64_t(pipe), bits_of(o.lambda),
+        0};
     return run_sweeps(pl, key, use_graph, o.n_iter, prof, s, sweep);
 }
 
 template <typename T>
 static int drop_dispatch_chord(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
-                               const pct_drop_opts &o, void *ws, hipStream_t s)
+                               const pct_drop_opts &o, void *ws, size_t wsb_, hipStream_t s)
 {
     switch (o.chord) {
-    case PCT_CHORD_F32: return drop_loop<T, PCT_CHORD_F32>(pl, p, n, b, x, o, ws, s);
-    case PCT_CHORD_F16: return drop_loop<T, PCT_CHORD_F16>(pl, p, n, b, x, o, ws, s);
-    case PCT_CHORD_BF16: return drop_loop<T, PCT_CHORD_BF16>(pl, p, n, b, x, o, ws, s);
-    default: return drop_loop<T, PCT_CHORD_F64>(pl, p, n, b, x, o, ws, s);
+    case PCT_CHORD_F32: return drop_loop<T, PCT_CHORD_F32>(pl, p, n, b, x, o, ws, wsb_, s);
+    case PCT_CHORD_F16: return drop_loop<T, PCT_CHORD_F16>(pl, p, n, b, x, o, ws, wsb_, s);
+    case PCT_CHORD_BF16: return drop_loop<T, PCT_CHORD_BF16>(pl, p, n, b, x, o, ws, wsb_, s);
+    default: return drop_loop<T, PCT_CHORD_F64>(pl, p, n, b, x, o, ws, wsb_, s);
     }
 }
 
 int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x, const pct_drop_opts &o,
-                void *ws, void *stream)
+                void *ws, size_t ws_bytes, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (o.dtype == PCT_F64) return drop_dispatch_chord<double>(pl, p, n, b, static_cast<double *>(x), o, ws, s);
-    return drop_dispatch_chord<float>(pl, p, n, b, static_cast<float *>(x), o, ws, s);
+    if (o.dtype == PCT_F64)
+        return drop_dispatch_chord<double>(pl, p, n, b, static_cast<double *>(x), o, ws, ws_bytes, s);
+    return drop_dispatch_chord<float>(pl, p, n, b, static_cast<float *>(x), o, ws, ws_bytes, s);
 }
 
 int launch_span_histogram(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_t *hist, void *stream)

@@ -156,7 +156,7 @@ def test_compute_calls_validate_before_device(plan):
 
 
 @pytest.mark.parametrize("field,value", [("block", 0), ("lambda_", 0.0), ("lambda_", float("inf")), ("n_iter", -1),
-                                         ("dtype", 3), ("chord", 9), ("flags", 0x10), ("block_begin", -1),
+                                         ("dtype", 3), ("chord", 9), ("flags", 0x20), ("block_begin", -1),
                                          ("block_end", 2), ("block_begin", 3), ("lanes", 2), ("lanes", 128),
                                          ("reserved", 1)])
 def test_drop_options_validated(plan, field, value):
@@ -250,7 +250,7 @@ def test_stored_row_calls_validate(plan):
     ok = _lib.make_opts(64, 0.1, 1, 0, chord="f16")
     run = L.pct_drop_iterate_rows
     assert run(plan, C.byref(rows), v, v, C.byref(ok), FAKE_WS, nb, None) == -2       # valid up to the workspace
-    for field, value in (("chord", 1), ("lanes", 8), ("block", 0), ("reserved", 1), ("flags", 0x10),
+    for field, value in (("chord", 1), ("lanes", 8), ("block", 0), ("reserved", 1), ("flags", 0x20),
                          ("block_end", 3)):
         o = _lib.make_opts(64, 0.1, 1, 0, chord="f16")
         setattr(o, field, value)

@@ -539,6 +539,54 @@ def test_fused_commit_is_bitwise_the_separate_schedule():
     assert_status_clean(plan)
 
 
+def test_traced_ahead_schedule_is_bitwise_the_fused_one():
+    # with 64 lanes per proton the rows of block t+1 are traced in the launch
+    # of block t; the DROP arithmetic is unchanged, so the result must be
+    # bitwise that of the plain fused schedule and of the separate one, for
+    # any block range, graph or per-block launches, repeated sweeps, and rows
+    # that overflow a lane's stash (they are walked again)
+    from paper_1802_01070_amd._lib import PCT_DROP_NO_GRAPH, PCT_DROP_NO_TRACE_AHEAD, PCT_DROP_SEPARATE_COMMIT
+    c = synth.CONFIGS[2]
+    sc = scan(2, 64000)
+    plan, pr = gpu_setup(sc)
+    b = torch.from_numpy(sc.b).to(DEV)
+    x0 = torch.from_numpy(np.random.default_rng(19).uniform(0.9, 1.1, sc.grid.nvox).astype(np.float32)).to(DEV)
+    for begin, end, iters, flags in [(0, 1, 1, 0), (0, 2, 2, 0), (3, 6, 3, PCT_DROP_NO_GRAPH), (0, 7, 1, 0),
+                                     (5, 20, 2, 0), (0, -1, 2, PCT_DROP_NO_GRAPH)]:
+        say(f"  traced ahead vs fused: blocks [{begin},{end}) iters={iters} flags={flags}")
+        out = []
+        for extra in (0, PCT_DROP_NO_TRACE_AHEAD, PCT_DROP_SEPARATE_COMMIT):
+            x = x0.clone()
+            api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=iters, block_begin=begin,
+                                 block_end=end, lanes=64, flags=flags | extra)
+            out.append(x)
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+    assert_status_clean(plan)
+    # steep rows: non-monotone paths are walked whole by lane 0 and overflow
+    # its stash, so every row goes through the walk-again branch
+    grid = Grid(16, 16, 2)
+    mlp = MLPModel(u_in=-6.0, u_out=6.0, step=1.0)
+    rays = [(-1.0 + 0.3 * k, 0.1 * k - 0.5, 3.0, 0.0, -1.0 + 0.2 * k, 0.5 - 0.1 * k, -3.0, 0.0, 0.5236)
+            for k in range(6)]
+    rays += [(0.2 * k - 2.0, 0.3, 0.01, 0.0, 0.2 * k - 2.0, 0.3, 0.01, 0.0, 0.5236) for k in range(10)]
+    pr_np = synth.make_rays(grid, mlp, rays)
+    plan2 = api.Plan(grid, mlp, DEV)
+    pr2 = api.Protons(pr_np, DEV)
+    b_np = np.linspace(3.0, 9.0, len(rays)).astype(np.float32)
+    b2 = torch.from_numpy(b_np).to(DEV)
+    xs = []
+    for extra in (0, PCT_DROP_NO_TRACE_AHEAD):
+        x = torch.ones(grid.nvox, dtype=torch.float32, device=DEV)
+        api.pct_drop_iterate(plan2, pr2, b2, x, block=4, lam=0.5, n_iter=2, lanes=64, flags=extra)
+        xs.append(x)
+    torch.cuda.synchronize()
+    assert torch.equal(xs[0], xs[1])
+    ref = oracle.drop(grid, mlp, pr_np, b_np, 1.0, block=4, lam=0.5, n_iter=2)
+    assert rsp_close(xs[0].double().cpu().numpy(), ref, 0) <= 1e-5
+    assert api.pct_device_status(plan2) & ~0x4 == 0
+
+
 def test_order_blocks_sorted_permutation_and_drop_unchanged():
     # within-block ordering is a per-block permutation sorted by (entry
     # slice, t_in, input position); DROP's block update is a sum over the
