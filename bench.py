@@ -64,11 +64,11 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of the block kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary of this workload, or None when the kernel
     sources changed since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", "traffic_k_drop_fused_cfg2.json")
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cfg2.json")
     if not os.path.exists(p):
         return None, "no counter summary"
     t = json.load(open(p))
@@ -164,6 +164,7 @@ def run_precision(args):
     plan = api.Plan(sc.grid, sc.mlp, dev)
     pr = api.Protons(sc.protons, dev)
     b = torch.from_numpy(sc.b).to(dev)
+    pr, b = api.pct_order_blocks(plan, pr, b, cfg.block)       # as the headline run does
     n_iter = cfg.n_iter
     runs = {}
     for name, dtype, chord in (("f64", torch.float64, "f64"), ("f32", torch.float32, "f32"),
@@ -524,7 +525,21 @@ def main():
         f"separate commit avg {c_avg_ms * 1e3:.2f} us ({c_n} sampled); host wall {t_host:.2f} s")
 
     ceiling = parallel_sweep_ceiling(api, plan, pr, x)
-    traffic, traffic_src = measured_traffic(cfg.name) if not args.protons else (None, "non-default size")
+    # which block schedule pct_drop_iterate takes (the library's rules): FP32
+    # with 64 lanes per proton and a workspace sized for the block (the Plan
+    # default covers blocks up to 8192) traces ahead; other FP32 runs fuse the
+    # commit; FP64 runs the block kernel and a separate commit
+    lanes = args.lanes or (64 if max(sc.grid.nx, sc.grid.ny) >= 160 else 32 if max(sc.grid.nx, sc.grid.ny) >= 64
+                           else 16)
+    if vdtype == torch.float32 and lanes == 64 and cfg.block <= 8192:
+        kname, kdesc = "k_drop_pipe", ("k_drop_pipe (trace of block t+1 into a row slot, DROP step of block t: "
+                                       "a.x + |a|^2 + rho + D-weighted scatter, commit of block t-1)")
+    elif vdtype == torch.float32:
+        kname, kdesc = "k_drop_fused", ("k_drop_fused (MLP trace + a.x + |a|^2 + rho + D-weighted scatter of "
+                                        "block t, commit of block t-1)")
+    else:
+        kname, kdesc = "k_drop_block", "k_drop_block (MLP trace + a.x + |a|^2 + rho + scatter) + k_drop_commit"
+    traffic, traffic_src = measured_traffic(cfg.name, kname) if not args.protons else (None, "non-default size")
 
     out = {
         "metric": "proton-iterations/sec (fused MLP+DROP) at 1 GPU",
@@ -557,8 +572,7 @@ def main():
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_source": traffic_src,
-            "kernel": ("k_drop_fused (MLP trace + a.x + |a|^2 + rho + D-weighted scatter of block t, commit of "
-                       "block t-1)") if c_n == 0 else "k_drop_block (MLP trace + a.x + |a|^2 + rho + scatter)",
+            "kernel": kdesc,
             "lanes_per_proton": args.lanes or "auto",
             "kernel_avg_us": k_avg_ms * 1e3,
             "kernel_avg_us_how": "timed region / block launches (HIP events on the sweep's stream)",
