@@ -134,6 +134,24 @@ typedef struct pct_plan pct_plan;
 int pct_plan_create(const pct_grid *grid, const pct_mlp *mlp, pct_plan **out);
 void pct_plan_destroy(pct_plan *plan);
 
+/* Object hull: the z-cylinder (x - cx)^2 + (y - cy)^2 < radius^2, lab mm. */
+typedef struct {
+    double cx, cy, radius;
+} pct_hull;
+
+/* Per-proton paths through a hull (Section I: the MLP is evaluated from where
+ * the proton enters the object to where it leaves it).  With hull != NULL
+ * every row is the straight entry track from the entry tracker plane to the
+ * hull, the most likely path between the points where the entry and exit
+ * tracks meet the hull (its own depth D, polynomial depth measured from the
+ * hull entry, vertices every `step` mm), and the straight exit track to the
+ * exit tracker plane; a track pair that does not cross the hull gives one
+ * straight segment between the tracker points.  Hull crossings outside the
+ * tracker planes are clamped to them.  NULL restores the tracker-to-tracker
+ * MLP of the shared table.  Host only; no work using the plan may be in
+ * flight.  radius must be finite and > 0, the centre finite. */
+int pct_plan_set_hull(pct_plan *plan, const pct_hull *hull);
+
 /* Number of polyline segments K (vertices 0..K). */
 int pct_plan_segments(const pct_plan *plan, int32_t *K);
 

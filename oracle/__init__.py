@@ -74,6 +74,10 @@ def lib():
         L.orc_trace.argtypes = [P(_Grid), P(_MLP), P(d), P(_Protons), i64, i64, P(i32), P(d)]
         L.orc_trace.restype = i64
         L.orc_trace_batch.argtypes = [P(_Grid), P(_MLP), P(_Protons), i64, i64, i64, P(i32), P(d), P(i64)]
+        L.orc_set_hull.argtypes = [C.c_int, d, d, d]
+        L.orc_set_hull.restype = None
+        L.orc_path.argtypes = [P(_MLP), P(d), P(_Protons), i64, P(d), C.c_int]
+        L.orc_path.restype = C.c_int
         L.orc_round_chord.argtypes = [d, C.c_int]
         L.orc_round_chord.restype = d
         L.orc_row.argtypes = [P(_Grid), P(_MLP), P(_Protons), i64, C.c_int, i64, P(i32), P(d), P(i64)]
@@ -155,6 +159,25 @@ def vertices(mlp, protons: dict, i: int) -> np.ndarray:
     out = np.zeros((K + 1, 3))
     lib().orc_vertices(C.byref(_mlp(mlp)), _ptr(tab, C.c_double), C.byref(pv.s), i, _ptr(out, C.c_double))
     return out
+
+
+def set_hull(radius: Optional[float], cx: float = 0.0, cy: float = 0.0):
+    """Per-proton paths through the z-cylinder hull of the given radius
+    (None: tracker-to-tracker paths).  Process-wide setting of the oracle."""
+    if radius is None:
+        lib().orc_set_hull(0, 0.0, 0.0, 0.0)
+    else:
+        lib().orc_set_hull(1, float(cx), float(cy), float(radius))
+
+
+def path(mlp, protons: dict, i: int) -> np.ndarray:
+    """Vertices (n, 3) of proton i's polyline (hull setting applies)."""
+    pv = _ProtonView(protons)
+    K = num_segments(mlp)
+    tab = mlp_table(mlp).ravel().copy()
+    P = np.zeros((K + 3) * 3)
+    n = lib().orc_path(C.byref(_mlp(mlp)), _ptr(tab, C.c_double), C.byref(pv.s), int(i), _ptr(P, C.c_double), K + 3)
+    return P[:3 * n].reshape(n, 3)
 
 
 def trace(grid, mlp, protons: dict, first: int = 0, count: Optional[int] = None, cap: int = 1024):

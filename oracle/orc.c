@@ -291,21 +291,120 @@ static void walk_segment(const orc_grid *g, const double P0[3], const double P1[
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Object hull (reading of Section I: the MLP runs between the points where   */
+/* the proton enters and leaves the object; the tracks are straight outside). */
+/* ------------------------------------------------------------------------ */
+static int g_hull = 0;
+static double g_hx = 0.0, g_hy = 0.0, g_hr = 0.0;
+
+/* on != 0: hull = z-cylinder (x-cx)^2 + (y-cy)^2 < r^2 (lab mm). */
+void orc_set_hull(int on, double cx, double cy, double r)
+{
+    g_hull = on;
+    g_hx = cx;
+    g_hy = cy;
+    g_hr = r;
+}
+
+/* Depth u where the straight track t(u) = t0 + th (u - u0) at gantry angle
+ * phi meets the hull circle: the first (smaller) or second root of
+ * |(u cos - t sin, u sin + t cos) - c|^2 = r^2.  Returns 0 if it misses. */
+static int hull_cross(const orc_rec *r, double t0, double th, double u0, int first, double *u)
+{
+    double cs = cos(r->phi), sn = sin(r->phi);
+    /* point at depth u: (u cs - (t0 + th (u - u0)) sn, u sn + (t0 + th (u - u0)) cs) */
+    double px = -(t0 - th * u0) * sn - g_hx, py = (t0 - th * u0) * cs - g_hy;   /* at u = 0 */
+    double dx = cs - th * sn, dy = sn + th * cs;                                /* per unit u */
+    double A = dx * dx + dy * dy;
+    double B = 2.0 * (px * dx + py * dy);
+    double C = px * px + py * py - g_hr * g_hr;
+    double disc = B * B - 4.0 * A * C;
+    if (!(disc > 0.0) || !(A > 0.0)) return 0;
+    double sq = sqrt(disc);
+    *u = first ? (-B - sq) / (2.0 * A) : (-B + sq) / (2.0 * A);
+    return 1;
+}
+
+/* Vertices of proton i's polyline into P (3 doubles each, room for `cap`
+ * vertices); returns their number.  Without a hull: the K+1 vertices of the
+ * shared table.  With a hull: entry tracker point (if the hull entry lies
+ * past the entry plane), the MLP from the hull entry to the hull exit with its
+ * own table (depth D = hull exit - hull entry, polynomial depth from the hull
+ * entry), exit tracker point (if the hull exit lies before the exit plane);
+ * a track pair that misses the hull gives the two tracker points. */
+int orc_path(const orc_mlp *m, const double *tab, const orc_protons *p, int64_t i, double *P, int cap)
+{
+    orc_rec r = load_rec(p, i);
+    int K = orc_num_segments(m);
+    if (!g_hull) {
+        if (K + 1 > cap) return -1;
+        for (int k = 0; k <= K; k++) vertex(m, tab, &r, k, P + 3 * k);
+        return K + 1;
+    }
+    double cs = cos(r.phi), sn = sin(r.phi);
+    double u1, u2;
+    int hit = hull_cross(&r, r.t_in, r.th_in, m->u_in, 1, &u1) && hull_cross(&r, r.t_out, r.th_out, m->u_out, 0, &u2);
+    if (hit) {
+        if (u1 < m->u_in) u1 = m->u_in;
+        if (u1 > m->u_out) u1 = m->u_out;
+        if (u2 < m->u_in) u2 = m->u_in;
+        if (u2 > m->u_out) u2 = m->u_out;
+    }
+    int n = 0;
+    if (!hit || !(u2 > u1)) {
+        if (cap < 2) return -1;
+        double ts[2] = {r.t_in, r.t_out}, vs[2] = {r.v_in, r.v_out}, us[2] = {m->u_in, m->u_out};
+        for (int q = 0; q < 2; q++) {
+            P[3 * q] = us[q] * cs - ts[q] * sn;
+            P[3 * q + 1] = us[q] * sn + ts[q] * cs;
+            P[3 * q + 2] = vs[q];
+        }
+        return 2;
+    }
+    /* the sub-problem between the hull crossings, states carried along the tracks */
+    orc_mlp m2 = *m;
+    m2.u_in = u1;
+    m2.u_out = u2;
+    orc_rec r2 = r;
+    r2.t_in = r.t_in + r.th_in * (u1 - m->u_in);
+    r2.v_in = r.v_in + r.ph_in * (u1 - m->u_in);
+    r2.t_out = r.t_out + r.th_out * (u2 - m->u_out);
+    r2.v_out = r.v_out + r.ph_out * (u2 - m->u_out);
+    int K2 = orc_num_segments(&m2);
+    if (K2 + 3 > cap) return -1;
+    if (u1 > m->u_in) {
+        P[0] = m->u_in * cs - r.t_in * sn;
+        P[1] = m->u_in * sn + r.t_in * cs;
+        P[2] = r.v_in;
+        n = 1;
+    }
+    double *tab2 = (double *)malloc(sizeof(double) * 4 * (K2 + 1));
+    orc_mlp_table(&m2, tab2);
+    for (int k = 0; k <= K2; k++) vertex(&m2, tab2, &r2, k, P + 3 * (n + k));
+    free(tab2);
+    n += K2 + 1;
+    if (u2 < m->u_out) {
+        P[3 * n] = m->u_out * cs - r.t_out * sn;
+        P[3 * n + 1] = m->u_out * sn + r.t_out * cs;
+        P[3 * n + 2] = r.v_out;
+        n++;
+    }
+    return n;
+}
+
 /* Ordered emission list of proton i.  Returns the full list length; entries
  * beyond `cap` are not written. */
 int64_t orc_trace(const orc_grid *g, const orc_mlp *m, const double *tab, const orc_protons *p, int64_t i,
                   int64_t cap, int32_t *vox, double *chord)
 {
-    orc_rec r = load_rec(p, i);
     int K = orc_num_segments(m);
+    int vcap = K + 3;
+    double *P = (double *)malloc(sizeof(double) * 3 * vcap);
+    int nv = orc_path(m, tab, p, i, P, vcap);
     orc_list L = {vox, chord, 0, cap, -1};
-    double P0[3], P1[3];
-    vertex(m, tab, &r, 0, P0);
-    for (int k = 0; k < K; k++) {
-        vertex(m, tab, &r, k + 1, P1);
-        walk_segment(g, P0, P1, &L);
-        P0[0] = P1[0]; P0[1] = P1[1]; P0[2] = P1[2];
-    }
+    for (int k = 0; k + 1 < nv; k++) walk_segment(g, P + 3 * k, P + 3 * (k + 1), &L);
+    free(P);
     return L.n;
 }
 

@@ -28,7 +28,7 @@ EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan
            "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read",
            "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
            "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows",
-           "pct_order_blocks")
+           "pct_order_blocks", "pct_plan_set_hull")
 
 
 class PctError(RuntimeError):
@@ -49,6 +49,10 @@ class pct_mlp(C.Structure):
 
 class pct_protons(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in FIELDS] + [("n", C.c_int64)]
+
+
+class pct_hull(C.Structure):
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("radius", C.c_double)]
 
 
 class pct_protons_buf(C.Structure):
@@ -101,6 +105,7 @@ def lib() -> C.CDLL:
             "pct_slice_span_histogram": ([vp, P(pct_protons), vp, vp, sz, vp], C.c_int),
             "pct_rows_count": ([vp, P(pct_protons), vp, vp, sz, vp], C.c_int),
             "pct_order_blocks": ([vp, P(pct_protons), vp, i64, P(pct_protons_buf), vp, vp], C.c_int),
+            "pct_plan_set_hull": ([vp, P(pct_hull)], C.c_int),
             "pct_rows_build": ([vp, P(pct_protons), i32, vp, vp, vp, vp, vp, sz, vp], C.c_int),
             "pct_drop_iterate_rows": ([vp, P(pct_rows), vp, vp, P(pct_drop_opts), vp, sz, vp], C.c_int),
         }

@@ -65,6 +65,14 @@ class Plan:
         self.ws_ptr = C.c_void_p(self.ws.data_ptr() + off)
         check(lib().pct_plan_upload(h, self.ws_ptr, self.ws_bytes, _stream(self.device)), "pct_plan_upload")
 
+    def set_hull(self, radius: Optional[float], cx: float = 0.0, cy: float = 0.0):
+        """Per-proton paths through the z-cylinder hull (pct_plan_set_hull);
+        radius None: tracker-to-tracker paths."""
+        h = None if radius is None else C.byref(_lib.pct_hull(float(cx), float(cy), float(radius)))
+        check(lib().pct_plan_set_hull(self.handle, h), "pct_plan_set_hull")
+        self.hull = None if radius is None else (float(cx), float(cy), float(radius))
+        return self
+
     def region(self, z_lo: int, z_hi: int) -> "Plan":
         """Plan of slices z_lo..z_hi of this grid (pct_plan_region)."""
         import dataclasses

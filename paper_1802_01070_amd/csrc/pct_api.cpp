@@ -60,6 +60,29 @@ GridDev grid_dev(const pct_grid &g)
     return d;
 }
 
+PathSrc path_src(const pct_plan &pl, const void *table_dev)
+{
+    PathSrc p{};
+    p.tab = static_cast<const double *>(table_dev);
+    p.K = pl.K;
+    p.nvmax = path_vertices_max(pl);
+    p.hull = pl.hull;
+    p.hx = pl.hull_c[0];
+    p.hy = pl.hull_c[1];
+    p.hr = pl.hull_r;
+    p.u_in = pl.mlp.u_in;
+    p.u_out = pl.mlp.u_out;
+    p.step = pl.mlp.step;
+    for (int k = 0; k < 6; ++k) p.poly[k] = pl.mlp.poly[k];
+    p.E0 = pl.mlp.E0;
+    p.X0 = pl.mlp.X0;
+    p.log_term = pl.mlp.log_term;
+    return p;
+}
+
+// tracker segment, hull-to-hull MLP (at most K segments), tracker segment
+int path_vertices_max(const pct_plan &pl) { return pl.K + 1 + (pl.hull ? 2 : 0); }
+
 // ---------------------------------------------------------------------------
 // MLP coefficient table
 //
@@ -247,6 +270,19 @@ void pct_plan_destroy(pct_plan *plan)
     profile_release(*plan);
     graph_release(*plan);
     delete plan;
+}
+
+int pct_plan_set_hull(pct_plan *plan, const pct_hull *hull)
+{
+    if (!plan) return PCT_ERR_INVALID_ARG;
+    if (hull && !(finite_pos(hull->radius) && std::isfinite(hull->cx) && std::isfinite(hull->cy)))
+        return PCT_ERR_INVALID_ARG;
+    graph_release(*plan);  // recorded sweeps use the other kernels
+    plan->hull = hull ? 1 : 0;
+    plan->hull_c[0] = hull ? hull->cx : 0.0;
+    plan->hull_c[1] = hull ? hull->cy : 0.0;
+    plan->hull_r = hull ? hull->radius : 0.0;
+    return PCT_OK;
 }
 
 int pct_plan_segments(const pct_plan *plan, int32_t *K)

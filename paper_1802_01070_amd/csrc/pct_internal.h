@@ -23,6 +23,23 @@ struct GridDev {
     double hi[3];  // origin + n*pitch
 };
 
+// How a proton's polyline is formed, passed to kernels by value.  Without a
+// hull the vertices come from the shared coefficient table (K segments from
+// tracker to tracker).  With a hull (the z-cylinder (x-hx)^2 + (y-hy)^2 <
+// hr^2) each proton's most likely path runs between the points where its
+// entry and exit tracks meet the hull, with its own coefficients, joined to
+// the tracker planes by straight segments along the measured tracks.
+struct PathSrc {
+    const double *tab;  // (K+1) * kRowDoubles, shared table
+    int K;              // tracker-to-tracker MLP segments
+    int nvmax;          // most vertices a proton's polyline can have
+    int hull;           // 0 or 1
+    double hx, hy, hr;  // hull centre and radius (mm)
+    double u_in, u_out, step;
+    double poly[6], E0, X0;
+    int log_term;
+};
+
 struct ProtonsDev {
     const float *t_in, *v_in, *th_in, *ph_in, *t_out, *v_out, *th_out, *ph_out, *gantry;
 };
@@ -73,12 +90,16 @@ struct pct_plan {
     void *graph_exec;
     std::vector<uint64_t> graph_key;
     void *capture_stream;  // private hipStream_t used only to record the graph
+    int hull;              // 1: per-proton MLP between the hull entry and exit points
+    double hull_c[2], hull_r;
 };
 
 namespace pct {
 
 // Launchers implemented in the HIP translation unit.  They assume validated
 // arguments and return a hipError_t value.
+PathSrc path_src(const pct_plan &pl, const void *table_dev);
+int path_vertices_max(const pct_plan &pl);
 int launch_trace(const pct_plan &pl, const ProtonsDev &p, int64_t first, int64_t count, int32_t max_nnz,
                  int32_t *vox, double *chord, int32_t *nnz, void *ws, void *stream);
 int launch_forward(const pct_plan &pl, const ProtonsDev &p, int64_t n, const void *x, int dtype, void *y,

@@ -87,9 +87,10 @@ struct TraceSink {
     }
 };
 
+template <bool HULL>
 __global__ void __launch_bounds__(kWG) k_trace(ProtonsDev p, int64_t first, int64_t count, int32_t max_nnz,
                                                int32_t *vox, double *chord, int32_t *nnz,
-                                               const double *__restrict__ tab, int K, GridDev g, unsigned *status)
+                                               const PathSrc src,  GridDev g, unsigned *status)
 {
     int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= count) return;
@@ -97,7 +98,7 @@ __global__ void __launch_bounds__(kWG) k_trace(ProtonsDev p, int64_t first, int6
     TraceSink ts{vox + q * max_nnz, chord + q * max_nnz, max_nnz, 0};
     if (rec_finite(r)) {
         Merge<TraceSink, PCT_CHORD_F64> m(ts, g);
-        walk_path(r, tab, K, g, m);
+        walk_path<HULL>(r, src, g, m);
         m.finish();
     } else {
         raise_status(status, PCT_DEV_NONFINITE);
@@ -131,9 +132,9 @@ struct DotSink {
     }
 };
 
-template <typename T>
+template <typename T, bool HULL>
 __global__ void __launch_bounds__(kWG) k_forward(ProtonsDev p, int64_t n, const T *__restrict__ x, T *y, T *nrm2,
-                                                 const double *__restrict__ tab, int K, GridDev g, unsigned *status)
+                                                 const PathSrc src,  GridDev g, unsigned *status)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(kWG) k_forward(ProtonsDev p, int64_t n, const 
     s.re.init(r);
     if (rec_finite(r)) {
         Merge<DotSink<T>, PCT_CHORD_F64> m(s, g);
-        walk_path(r, tab, K, g, m);
+        walk_path<HULL>(r, src, g, m);
         m.finish();
         if (s.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
     } else {
@@ -166,9 +167,9 @@ struct ScatterSink {
     __device__ __forceinline__ void final(int j, int, int, int, double c) { atomicAdd(g + j, T(r * c)); }
 };
 
-template <typename T>
+template <typename T, bool HULL>
 __global__ void __launch_bounds__(kWG) k_backproject(ProtonsDev p, int64_t n, const T *__restrict__ rv, T *gout,
-                                                     const double *__restrict__ tab, int K, GridDev g,
+                                                     const PathSrc src,  GridDev g,
                                                      unsigned *status)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -182,7 +183,7 @@ __global__ void __launch_bounds__(kWG) k_backproject(ProtonsDev p, int64_t n, co
     }
     ScatterSink<T> s{gout, ri};
     Merge<ScatterSink<T>, PCT_CHORD_F64> m(s, g);
-    walk_path(r, tab, K, g, m);
+    walk_path<HULL>(r, src, g, m);
     m.finish();
 }
 
@@ -279,10 +280,10 @@ __device__ __forceinline__ void publish_range(int jmin, int jmax, int *range)
     }
 }
 
-template <typename T, int CHORD>
+template <typename T, int CHORD, bool HULL>
 __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__restrict__ b,
                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
-                                                   const double *__restrict__ tab, int K, GridDev g, int64_t lo,
+                                                   const PathSrc src,  GridDev g, int64_t lo,
                                                    int64_t hi, double lambda, unsigned *status)
 {
     int64_t i = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -308,7 +309,7 @@ __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__
         s.re.init(r);
         {
             Merge<DotSink<T>, CHORD> m(s, g);
-            walk_path(r, tab, K, g, m);
+            walk_path<HULL>(r, src, g, m);
             m.finish();
         }
         if (s.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
@@ -319,7 +320,7 @@ __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__
             sc.rho = lambda * (bi - s.dot) / s.n2;
             sc.re.init(r);
             Merge<DropScatterSink<T>, CHORD> m(sc, g);
-            walk_path(r, tab, K, g, m);
+            walk_path<HULL>(r, src, g, m);
             m.finish();
         }
     }
@@ -364,6 +365,7 @@ __device__ __forceinline__ bool group_any(bool p)
 // signed coordinate along the dominant axis, A(k) = sgn * P[k][dom], increases
 // along a monotone path.
 struct GroupPath {
+    int K;           // segments of this proton's polyline
     int dom;         // dominant in-plane axis (0: x, 1: y)
     double sgn;      // direction of travel along it
     int s_lo, s_hi;  // dominant-axis index range crossed by the path (s_lo > s_hi: none)
@@ -375,17 +377,20 @@ __device__ __forceinline__ double path_A(const GroupPath &gp, const double *__re
     return gp.sgn * P[3 * k + gp.dom];
 }
 
-template <int LPP>
-__device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__restrict__ tab, int K,
-                                                const GridDev &g, double *__restrict__ P, int l, bool active)
+template <int LPP, bool HULL>
+__device__ __forceinline__ GroupPath stage_path(const Rec &r, const PathSrc &src, const GridDev &g,
+                                                double *__restrict__ P, int l, bool active)
 {
     GroupPath gp;
     gp.dom = fabs(r.cs) >= fabs(r.sn) ? 0 : 1;
     const double e = gp.dom == 0 ? r.cs : r.sn;
     gp.sgn = e > 0.0 ? 1.0 : -1.0;
+    const PathState ps = path_prepare<HULL>(r, src);
+    const int K = ps.nv - 1;
+    gp.K = K;
     for (int k = l; k <= K; k += LPP) {
         double v[3] = {0.0, 0.0, 0.0};
-        if (active) vertex(r, tab + k * kRowDoubles, v);
+        if (active) path_vertex<HULL>(r, src, ps, k, v);
         P[3 * k] = v[0];
         P[3 * k + 1] = v[1];
         P[3 * k + 2] = v[2];
@@ -415,9 +420,10 @@ __device__ __forceinline__ GroupPath stage_path(const Rec &r, const double *__re
 // run of segments clipped to the range.  A non-monotone path is walked whole
 // by lane 0.
 template <int LPP, class M>
-__device__ __forceinline__ void walk_lane(const GroupPath &gp, int l, int K, const GridDev &g,
+__device__ __forceinline__ void walk_lane(const GroupPath &gp, int l, const GridDev &g,
                                           const double *__restrict__ P, M &m)
 {
+    const int K = gp.K;
     const int a = gp.dom;
     if (gp.full) {
         if (l != 0 || gp.s_hi < gp.s_lo) return;
@@ -493,10 +499,10 @@ __host__ __device__ constexpr size_t stash_bytes()
 }
 
 // Fused DROP block kernel: one wave per workgroup, 64 / LPP protons per wave.
-template <typename T, int CHORD, int LPP>
+template <typename T, int CHORD, int LPP, bool HULL>
 __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__restrict__ b,
                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
-                                                   const double *__restrict__ tab, int K, GridDev g, int64_t lo,
+                                                   const PathSrc src,  GridDev g, int64_t lo,
                                                    int64_t hi, double lambda, unsigned *status)
 {
     using CT = typename std::conditional<sizeof(T) == 4, float, double>::type;
@@ -518,18 +524,18 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
         }
     }
     if (!active) r.cs = 1.0, r.sn = 0.0;
-    double *P = lds + grp * 3 * (K + 1);
-    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * (K + 1));
+    double *P = lds + grp * 3 * src.nvmax;
+    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * src.nvmax);
     int *sj = reinterpret_cast<int *>(stash);
     CT *sc = reinterpret_cast<CT *>(stash + size_t(64) * kStash * sizeof(int));
-    const GroupPath gp = stage_path<LPP>(r, tab, K, g, P, l, active);
+    const GroupPath gp = stage_path<LPP, HULL>(r, src, g, P, l, active);
 
     // one walk: ||a_i||^2, re-entries and the stash of pieces
     StashSink<CT, kStash> st{sj, sc, lane, {}, 0.0, 0};
     st.re.init(r);
     {
         Merge<StashSink<CT, kStash>, CHORD> m(st, g);
-        walk_lane<LPP>(gp, l, K, g, P, m);
+        walk_lane<LPP>(gp, l, g, P, m);
         m.finish();
     }
     if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
@@ -550,7 +556,7 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
         ds.n2 = 0.0;
         ds.re.init(r);
         Merge<DotSink<T>, CHORD> m(ds, g);
-        walk_lane<LPP>(gp, l, K, g, P, m);
+        walk_lane<LPP>(gp, l, g, P, m);
         m.finish();
         dot = ds.dot;
     }
@@ -584,7 +590,7 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
             sc2.jmax = -1;
             sc2.re.init(r);
             Merge<DropScatterSink<T>, CHORD> m(sc2, g);
-            walk_lane<LPP>(gp, l, K, g, P, m);
+            walk_lane<LPP>(gp, l, g, P, m);
             m.finish();
             jmin = sc2.jmin;
             jmax = sc2.jmax;
@@ -660,13 +666,13 @@ static_assert(kCommitWG % 8 == 0, "proton workgroups must start on XCD 0");
 
 // Four waves per SIMD (at most 128 VGPRs): the walk is latency-bound, and the
 // extra wave hides more latency than the few spilled registers cost.
-template <int CHORD, int LPP>
+template <int CHORD, int LPP, bool HULL>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) k_drop_fused(ProtonsDev p, const float *__restrict__ b,
                                                    const float *__restrict__ base, float *__restrict__ next,
                                                    const unsigned long long *__restrict__ pk_prev,
                                                    unsigned long long *pk_cur, unsigned long long *pk_old, int *r_cur,
                                                    const int *r_prev, const int *r_old, int *r_reset,
-                                                   const double *__restrict__ tab, int K, GridDev g, int64_t lo,
+                                                   const PathSrc src,  GridDev g, int64_t lo,
                                                    int64_t hi, double lambda, unsigned *status, int nvox)
 {
     if (int(blockIdx.x) < kCommitWG) {
@@ -701,17 +707,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
         }
     }
     if (!active) r.cs = 1.0, r.sn = 0.0;
-    double *P = lds + grp * 3 * (K + 1);
-    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * (K + 1));
+    double *P = lds + grp * 3 * src.nvmax;
+    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * src.nvmax);
     int *sj = reinterpret_cast<int *>(stash);
     CT *sc = reinterpret_cast<CT *>(stash + size_t(64) * kStash * sizeof(int));
-    const GroupPath gp = stage_path<LPP>(r, tab, K, g, P, l, active);
+    const GroupPath gp = stage_path<LPP, HULL>(r, src, g, P, l, active);
 
     StashSink<CT, kStash> st{sj, sc, lane, {}, 0.0, 0};
     st.re.init(r);
     {
         Merge<StashSink<CT, kStash>, CHORD> m(st, g);
-        walk_lane<LPP>(gp, l, K, g, P, m);
+        walk_lane<LPP>(gp, l, g, P, m);
         m.finish();
     }
     if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
@@ -732,7 +738,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
         ds.n2 = 0.0;
         ds.re.init(r);
         Merge<DotSink<float, LazyX>, CHORD> m(ds, g);
-        walk_lane<LPP>(gp, l, K, g, P, m);
+        walk_lane<LPP>(gp, l, g, P, m);
         m.finish();
         dot = ds.dot;
     }
@@ -759,7 +765,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
             sc2.jmax = -1;
             sc2.re.init(r);
             Merge<DropScatterSink<float>, CHORD> m(sc2, g);
-            walk_lane<LPP>(gp, l, K, g, P, m);
+            walk_lane<LPP>(gp, l, g, P, m);
             m.finish();
             jmin = sc2.jmin;
             jmax = sc2.jmax;
@@ -802,9 +808,9 @@ __host__ __device__ inline SlotDev slot_at(char *base, int64_t records)
 
 // Trace of record r of the block [wlo, whi) into slot wr (one proton per
 // one-wave workgroup).
-template <int CHORD>
-__device__ __forceinline__ void trace_role(const ProtonsDev &p, const SlotDev &wr, const double *__restrict__ tab,
-                                           int K, const GridDev &g, int64_t wlo, int64_t whi, int64_t r, double *P,
+template <int CHORD, bool HULL>
+__device__ __forceinline__ void trace_role(const ProtonsDev &p, const SlotDev &wr, const PathSrc src,
+                                            const GridDev &g, int64_t wlo, int64_t whi, int64_t r, double *P,
                                            int *sj, float *sc, unsigned *status)
 {
     const int lane = threadIdx.x;
@@ -818,12 +824,12 @@ __device__ __forceinline__ void trace_role(const ProtonsDev &p, const SlotDev &w
         rec.cs = 1.0;
         rec.sn = 0.0;
     }
-    const GroupPath gp = stage_path<64>(rec, tab, K, g, P, lane, active);
+    const GroupPath gp = stage_path<64, HULL>(rec, src, g, P, lane, active);
     StashSink<float, kStash> st{sj, sc, lane, {}, 0.0, 0};
     st.re.init(rec);
     {
         Merge<StashSink<float, kStash>, CHORD> m(st, g);
-        walk_lane<64>(gp, lane, K, g, P, m);
+        walk_lane<64>(gp, lane, g, P, m);
         m.finish();
     }
     if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
@@ -838,12 +844,12 @@ __device__ __forceinline__ void trace_role(const ProtonsDev &p, const SlotDev &w
     if (lane == 0) wr.n2[r] = active ? n2 : 0.0;
 }
 
-template <int CHORD>
+template <int CHORD, bool HULL>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_drop_pipe(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ base, float *__restrict__ next,
             const unsigned long long *__restrict__ pk_prev, unsigned long long *pk_cur, unsigned long long *pk_old,
             int *r_cur, const int *r_prev, const int *r_old, int *r_reset, SlotDev rd, SlotDev wr,
-            const double *__restrict__ tab, int K, GridDev g, int64_t lo, int64_t hi, int64_t wlo, int64_t whi,
+            const PathSrc src,  GridDev g, int64_t lo, int64_t hi, int64_t wlo, int64_t whi,
             int n_commit, double lambda, unsigned *status, int nvox)
 {
     const int bid = int(blockIdx.x);
@@ -853,7 +859,7 @@ k_drop_pipe(ProtonsDev p, const float *__restrict__ b, const float *__restrict__
     }
     extern __shared__ double lds[];
     double *P = lds;
-    char *stash = reinterpret_cast<char *>(lds + 3 * (K + 1));
+    char *stash = reinterpret_cast<char *>(lds + 3 * src.nvmax);
     int *sj = reinterpret_cast<int *>(stash);
     float *sc = reinterpret_cast<float *>(stash + size_t(64) * kStash * sizeof(int));
     const int lane = threadIdx.x;
@@ -863,7 +869,7 @@ k_drop_pipe(ProtonsDev p, const float *__restrict__ b, const float *__restrict__
     const int64_t per_xcd = (n_d + 7) / 8;
     const int64_t n_w8 = 8 * ((whi - wlo + 7) / 8);  // keeps the DROP workgroups XCD-aligned
     if (bid - n_commit < n_w8) {
-        trace_role<CHORD>(p, wr, tab, K, g, wlo, whi, int64_t(bid - n_commit), P, sj, sc, status);
+        trace_role<CHORD, HULL>(p, wr, src, g, wlo, whi, int64_t(bid - n_commit), P, sj, sc, status);
         return;
     }
     const int wq = int(bid - n_commit - n_w8);
@@ -908,7 +914,7 @@ k_drop_pipe(ProtonsDev p, const float *__restrict__ b, const float *__restrict__
             // lanes beyond the stash walk their slabs again (rare)
             if (active) rec = load_rec(p, i);
             if (!active) rec.cs = 1.0, rec.sn = 0.0;
-            gp = stage_path<64>(rec, tab, K, g, P, lane, active);
+            gp = stage_path<64, HULL>(rec, src, g, P, lane, active);
             if (spill) {
                 DotSink<float, LazyX> ds;
                 ds.x = xa;
@@ -916,7 +922,7 @@ k_drop_pipe(ProtonsDev p, const float *__restrict__ b, const float *__restrict__
                 ds.n2 = 0.0;
                 ds.re.init(rec);
                 Merge<DotSink<float, LazyX>, CHORD> m(ds, g);
-                walk_lane<64>(gp, lane, K, g, P, m);
+                walk_lane<64>(gp, lane, g, P, m);
                 m.finish();
                 dot = ds.dot;
             }
@@ -946,7 +952,7 @@ k_drop_pipe(ProtonsDev p, const float *__restrict__ b, const float *__restrict__
                 sc2.jmax = -1;
                 sc2.re.init(rec);
                 Merge<DropScatterSink<float>, CHORD> m(sc2, g);
-                walk_lane<64>(gp, lane, K, g, P, m);
+                walk_lane<64>(gp, lane, g, P, m);
                 m.finish();
                 jmin = sc2.jmin;
                 jmax = sc2.jmax;
@@ -1241,8 +1247,9 @@ struct CountSink {
 };
 
 // Row lengths (after consecutive merge) into offsets[1..n].
+template <bool HULL>
 __global__ void __launch_bounds__(kWG) k_row_lengths(ProtonsDev p, int64_t n, long long *len_out,
-                                                     const double *__restrict__ tab, int K, GridDev g,
+                                                     const PathSrc src,  GridDev g,
                                                      unsigned *status)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1251,7 +1258,7 @@ __global__ void __launch_bounds__(kWG) k_row_lengths(ProtonsDev p, int64_t n, lo
     CountSink cs{0};
     if (rec_finite(r)) {
         Merge<CountSink, PCT_CHORD_F64> m(cs, g);
-        walk_path(r, tab, K, g, m);
+        walk_path<HULL>(r, src, g, m);
         m.finish();
     } else {
         raise_status(status, PCT_DEV_NONFINITE);
@@ -1354,10 +1361,10 @@ struct RowSink {
     }
 };
 
-template <int CT>
+template <int CT, bool HULL>
 __global__ void __launch_bounds__(kWG) k_rows_build(ProtonsDev p, int64_t n, const long long *__restrict__ offsets,
                                                     int32_t *vox, typename StoredChord<CT>::type *chord, double *n2,
-                                                    const double *__restrict__ tab, int K, GridDev g,
+                                                    const PathSrc src,  GridDev g,
                                                     unsigned *status)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1367,7 +1374,7 @@ __global__ void __launch_bounds__(kWG) k_rows_build(ProtonsDev p, int64_t n, con
     rs.re.init(r);
     if (rec_finite(r)) {
         Merge<RowSink<CT>, CT> m(rs, g);
-        walk_path(r, tab, K, g, m);
+        walk_path<HULL>(r, src, g, m);
         m.finish();
         if (rs.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
     } else {
@@ -1581,10 +1588,14 @@ int launch_trace(const pct_plan &pl, const ProtonsDev &p, int64_t first, int64_t
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
-    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    const PathSrc src = path_src(pl, wsb(ws) + L.table);
     unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
-    hipLaunchKernelGGL(k_trace, dim3(grid_for(count)), dim3(kWG), 0, s, p, first, count, max_nnz, vox, chord, nnz,
-                       tab, pl.K, grid_dev(pl.grid), status);
+    if (src.hull)
+        hipLaunchKernelGGL(k_trace<true>, dim3(grid_for(count)), dim3(kWG), 0, s, p, first, count, max_nnz, vox,
+                           chord, nnz, src, grid_dev(pl.grid), status);
+    else
+        hipLaunchKernelGGL(k_trace<false>, dim3(grid_for(count)), dim3(kWG), 0, s, p, first, count, max_nnz, vox,
+                           chord, nnz, src, grid_dev(pl.grid), status);
     return hipGetLastError();
 }
 
@@ -1593,16 +1604,24 @@ int launch_forward(const pct_plan &pl, const ProtonsDev &p, int64_t n, const voi
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
-    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    const PathSrc src = path_src(pl, wsb(ws) + L.table);
     unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
     GridDev g = grid_dev(pl.grid);
-    if (dtype == PCT_F64)
-        hipLaunchKernelGGL(k_forward<double>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
-                           static_cast<const double *>(x), static_cast<double *>(y), static_cast<double *>(nrm2),
-                           tab, pl.K, g, status);
+    auto go = [&](auto hull) {
+        constexpr bool H = decltype(hull)::value;
+        if (dtype == PCT_F64)
+            hipLaunchKernelGGL((k_forward<double, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
+                               static_cast<const double *>(x), static_cast<double *>(y),
+                               static_cast<double *>(nrm2), src, g, status);
+        else
+            hipLaunchKernelGGL((k_forward<float, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
+                               static_cast<const float *>(x), static_cast<float *>(y), static_cast<float *>(nrm2),
+                               src, g, status);
+    };
+    if (src.hull)
+        go(std::true_type{});
     else
-        hipLaunchKernelGGL(k_forward<float>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, static_cast<const float *>(x),
-                           static_cast<float *>(y), static_cast<float *>(nrm2), tab, pl.K, g, status);
+        go(std::false_type{});
     return hipGetLastError();
 }
 
@@ -1611,15 +1630,22 @@ int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
-    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    const PathSrc src = path_src(pl, wsb(ws) + L.table);
     unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
     GridDev g = grid_dev(pl.grid);
-    if (dtype == PCT_F64)
-        hipLaunchKernelGGL(k_backproject<double>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
-                           static_cast<const double *>(r), static_cast<double *>(gout), tab, pl.K, g, status);
+    auto go = [&](auto hull) {
+        constexpr bool H = decltype(hull)::value;
+        if (dtype == PCT_F64)
+            hipLaunchKernelGGL((k_backproject<double, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
+                               static_cast<const double *>(r), static_cast<double *>(gout), src, g, status);
+        else
+            hipLaunchKernelGGL((k_backproject<float, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
+                               static_cast<const float *>(r), static_cast<float *>(gout), src, g, status);
+    };
+    if (src.hull)
+        go(std::true_type{});
     else
-        hipLaunchKernelGGL(k_backproject<float>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
-                           static_cast<const float *>(r), static_cast<float *>(gout), tab, pl.K, g, status);
+        go(std::false_type{});
     return hipGetLastError();
 }
 
@@ -1674,19 +1700,21 @@ void profile_release(pct_plan &pl)
 }
 
 // Launch of one block's fused kernel with the chosen lanes per proton.
-template <typename T, int CHORD>
+template <typename T, int CHORD, bool HULL>
 static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, T *x, void *acc, int32_t *cnt,
-                         int *range, const double *tab, int K, const GridDev &g, int64_t lo, int64_t hi,
+                         int *range, const PathSrc &src, const GridDev &g, int64_t lo, int64_t hi,
                          double lambda, unsigned *status)
 {
     const int64_t n = hi - lo;
     switch (lanes) {
 #define PCT_LAUNCH_LPP(LPP)                                                                                      \
     case LPP: {                                                                                                  \
-        const unsigned grid = unsigned((n + (64 / LPP) - 1) / (64 / LPP));                                    \
-        const size_t lds = size_t(64 / LPP) * 3 * size_t(K + 1) * sizeof(double) + stash_bytes<T>();          \
-        hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP>), dim3(grid), dim3(64), lds, s, p, b, x, acc, cnt,       \
-                           range, tab, K, g, lo, hi, lambda, status);                                             \
+        if constexpr (!HULL || LPP == 64) {                                                                      \
+            const unsigned grid = unsigned((n + (64 / LPP) - 1) / (64 / LPP));                                \
+            const size_t lds = size_t(64 / LPP) * 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<T>();  \
+            hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, acc, \
+                               cnt, range, src, g, lo, hi, lambda, status);                                     \
+        }                                                                                                        \
         break;                                                                                                   \
     }
         PCT_LAUNCH_LPP(8)
@@ -1695,30 +1723,32 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
         PCT_LAUNCH_LPP(64)
 #undef PCT_LAUNCH_LPP
     default:
-        hipLaunchKernelGGL((k_drop_rows<T, CHORD>), dim3(grid_for(n)), dim3(kWG), 0, s, p, b, x, acc, cnt, range,
-                           tab, K, g, lo, hi, lambda, status);
+        hipLaunchKernelGGL((k_drop_rows<T, CHORD, HULL>), dim3(grid_for(n)), dim3(kWG), 0, s, p, b, x, acc, cnt,
+                           range, src, g, lo, hi, lambda, status);
     }
 }
 
 // Launch q of a fused FP32 sweep (see k_drop_fused): commit workgroups first,
 // then the proton workgroups of block [lo, hi).
-template <int CHORD>
+template <int CHORD, bool HULL>
 static void launch_fused(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, const float *base,
                          float *next, const unsigned long long *pk_prev, unsigned long long *pk_cur,
                          unsigned long long *pk_old, int *r_cur, const int *r_prev, const int *r_old, int *r_reset,
-                         const double *tab, int K, const GridDev &g, int64_t lo, int64_t hi, double lambda,
+                         const PathSrc &src, const GridDev &g, int64_t lo, int64_t hi, double lambda,
                          unsigned *status, int nvox)
 {
     const int64_t n = hi - lo;
     switch (lanes) {
 #define PCT_LAUNCH_FUSED(LPP)                                                                                    \
     case LPP: {                                                                                                  \
-        const int64_t n_wg = (n + (64 / LPP) - 1) / (64 / LPP);                                              \
-        const unsigned grid = unsigned(kCommitWG + 8 * ((n_wg + 7) / 8));                                    \
-        const size_t lds = size_t(64 / LPP) * 3 * size_t(K + 1) * sizeof(double) + stash_bytes<float>();      \
-        hipLaunchKernelGGL((k_drop_fused<CHORD, LPP>), dim3(grid), dim3(64), lds, s, p, b, base, next, pk_prev,  \
-                           pk_cur, pk_old, r_cur, r_prev, r_old, r_reset, tab, K, g, lo, hi, lambda, status,     \
-                           nvox);                                                                                \
+        if constexpr (!HULL || LPP == 64) {                                                                      \
+            const int64_t n_wg = (n + (64 / LPP) - 1) / (64 / LPP);                                          \
+            const unsigned grid = unsigned(kCommitWG + 8 * ((n_wg + 7) / 8));                                \
+            const size_t lds = size_t(64 / LPP) * 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<float>(); \
+            hipLaunchKernelGGL((k_drop_fused<CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, base, next, \
+                               pk_prev, pk_cur, pk_old, r_cur, r_prev, r_old, r_reset, src, g, lo, hi, lambda,  \
+                               status, nvox);                                                                    \
+        }                                                                                                        \
         break;                                                                                                   \
     }
         PCT_LAUNCH_FUSED(8)
@@ -1740,7 +1770,9 @@ static int choose_lanes(const pct_plan &pl, int requested)
         const int ndom = std::max(pl.grid.nx, pl.grid.ny);
         lanes = ndom >= 160 ? 64 : ndom >= 64 ? 32 : 16;
     }
-    if (lanes > 1 && size_t(64 / lanes) * 3 * size_t(pl.K + 1) * sizeof(double) + stash_bytes<double>() > kLdsBudget)
+    if (pl.hull && lanes != 1) lanes = 64;  // the hull instantiations use 64 lanes per proton
+    if (lanes > 1 && size_t(64 / lanes) * 3 * size_t(path_vertices_max(pl)) * sizeof(double) + stash_bytes<double>() >
+                         kLdsBudget)
         lanes = 1;
     return lanes;
 }
@@ -1873,7 +1905,7 @@ static inline uint64_t bits_of(double v)
     return u;
 }
 
-template <typename T, int CHORD>
+template <typename T, int CHORD, bool HULL>
 static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
                      const pct_drop_opts &o, void *ws, size_t ws_bytes, hipStream_t s)
 {
@@ -1886,7 +1918,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
     const int64_t nblk = o.block_end - o.block_begin;
     const int64_t every = std::max<int64_t>(1, (nblk + kProfSamples - 1) / kProfSamples);
     Layout L = layout_for(pl.nvox, pl.K, o.dtype);
-    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    const PathSrc src = path_src(pl, wsb(ws) + L.table);
     unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
     int *hdr = reinterpret_cast<int *>(wsb(ws) + L.hdr);
     void *acc = wsb(ws) + L.acc;
@@ -1906,7 +1938,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
             int *r_next = hdr + (seq % 2 == 0 ? kHdrRange1 : kHdrRange0);
             const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
             if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
-            launch_block<T, CHORD>(lanes, s, p, b, x, acc, cnt, r_this, tab, pl.K, g, lo, hi, o.lambda, status);
+            launch_block<T, CHORD, HULL>(lanes, s, p, b, x, acc, cnt, r_this, src, g, lo, hi, o.lambda, status);
             if (sample) {
                 (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
                 pl.prof_used[0]++;
@@ -1928,7 +1960,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                 const FusedBufs F = fused_bufs(pl, ws, x);
                 SlotDev slot[2] = {slot_at(wsb(ws) + L.total, o.block),
                                    slot_at(wsb(ws) + L.total + slot_bytes(o.block), o.block)};
-                const size_t lds = 3 * size_t(pl.K + 1) * sizeof(double) + stash_bytes<float>();
+                const size_t lds = 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<float>();
                 auto block_range = [&](int64_t t, int64_t &a, int64_t &e) {
                     a = e = 0;
                     if (t < o.block_end) {
@@ -1941,20 +1973,20 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                                   int64_t wlo, whi;
                                   if (q == 0) {  // prologue: trace the first block
                                       block_range(o.block_begin, wlo, whi);
-                                      hipLaunchKernelGGL((k_drop_pipe<CHORD>), dim3(unsigned(8 * ((whi - wlo + 7) / 8))),
+                                      hipLaunchKernelGGL((k_drop_pipe<CHORD, HULL>), dim3(unsigned(8 * ((whi - wlo + 7) / 8))),
                                                          dim3(64),
                                                          lds, s, p, b, f.base, f.next, f.pk_prev, f.pk_cur,
                                                          f.pk_old, f.r_cur, f.r_prev, f.r_old, f.r_reset, slot[1],
-                                                         slot[0], tab, pl.K, g, int64_t(0), int64_t(0), wlo, whi, 0,
+                                                         slot[0], src, g, int64_t(0), int64_t(0), wlo, whi, 0,
                                                          o.lambda, status, F.nv);
                                   }
                                   block_range(o.block_begin + q + 1, wlo, whi);
                                   const int64_t n_d = hi - lo;
                                   const unsigned grid =
                                       unsigned(kCommitWG + 8 * ((whi - wlo + 7) / 8) + 8 * ((n_d + 7) / 8));
-                                  hipLaunchKernelGGL((k_drop_pipe<CHORD>), dim3(grid), dim3(64), lds, s, p, b, f.base,
+                                  hipLaunchKernelGGL((k_drop_pipe<CHORD, HULL>), dim3(grid), dim3(64), lds, s, p, b, f.base,
                                                      f.next, f.pk_prev, f.pk_cur, f.pk_old, f.r_cur, f.r_prev,
-                                                     f.r_old, f.r_reset, slot[q % 2], slot[(q + 1) % 2], tab, pl.K,
+                                                     f.r_old, f.r_reset, slot[q % 2], slot[(q + 1) % 2], src,
                                                      g, lo, hi, wlo, whi, kCommitWG, o.lambda, status, F.nv);
                               });
                 return;
@@ -1963,8 +1995,8 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                 const FusedBufs F = fused_bufs(pl, ws, x);
                 enqueue_fused(pl, F, o.block_begin, o.block_end, o.block, n, s, record_events, every,
                               [&](hipStream_t s, int64_t, int64_t lo, int64_t hi, const FusedStep &f) {
-                                  launch_fused<CHORD>(lanes, s, p, b, f.base, f.next, f.pk_prev, f.pk_cur, f.pk_old,
-                                                      f.r_cur, f.r_prev, f.r_old, f.r_reset, tab, pl.K, g, lo, hi,
+                                  launch_fused<CHORD, HULL>(lanes, s, p, b, f.base, f.next, f.pk_prev, f.pk_cur, f.pk_old,
+                                                      f.r_cur, f.r_prev, f.r_old, f.r_reset, src, g, lo, hi,
                                                       o.lambda, status, F.nv);
                               });
                 return;
@@ -1990,12 +2022,16 @@ template <typename T>
 static int drop_dispatch_chord(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, T *x,
                                const pct_drop_opts &o, void *ws, size_t wsb_, hipStream_t s)
 {
-    switch (o.chord) {
-    case PCT_CHORD_F32: return drop_loop<T, PCT_CHORD_F32>(pl, p, n, b, x, o, ws, wsb_, s);
-    case PCT_CHORD_F16: return drop_loop<T, PCT_CHORD_F16>(pl, p, n, b, x, o, ws, wsb_, s);
-    case PCT_CHORD_BF16: return drop_loop<T, PCT_CHORD_BF16>(pl, p, n, b, x, o, ws, wsb_, s);
-    default: return drop_loop<T, PCT_CHORD_F64>(pl, p, n, b, x, o, ws, wsb_, s);
-    }
+    auto go = [&](auto hull) -> int {
+        constexpr bool H = decltype(hull)::value;
+        switch (o.chord) {
+        case PCT_CHORD_F32: return drop_loop<T, PCT_CHORD_F32, H>(pl, p, n, b, x, o, ws, wsb_, s);
+        case PCT_CHORD_F16: return drop_loop<T, PCT_CHORD_F16, H>(pl, p, n, b, x, o, ws, wsb_, s);
+        case PCT_CHORD_BF16: return drop_loop<T, PCT_CHORD_BF16, H>(pl, p, n, b, x, o, ws, wsb_, s);
+        default: return drop_loop<T, PCT_CHORD_F64, H>(pl, p, n, b, x, o, ws, wsb_, s);
+        }
+    };
+    return pl.hull ? go(std::true_type{}) : go(std::false_type{});
 }
 
 int launch_drop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *b, void *x, const pct_drop_opts &o,
@@ -2061,13 +2097,17 @@ int launch_rows_count(const pct_plan &pl, const ProtonsDev &p, int64_t n, int64_
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
-    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    const PathSrc src = path_src(pl, wsb(ws) + L.table);
     unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
     long long *partial = reinterpret_cast<long long *>(wsb(ws) + L.partial);
     long long *off = reinterpret_cast<long long *>(offsets);
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, off, int64_t(1));
     if (n > 0) {
-        hipLaunchKernelGGL(k_row_lengths, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off + 1, tab, pl.K,
+if (src.hull)
+                    hipLaunchKernelGGL(k_row_lengths<true>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off + 1, src,
+                           grid_dev(pl.grid), status);
+        else
+                    hipLaunchKernelGGL(k_row_lengths<false>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off + 1, src,
                            grid_dev(pl.grid), status);
         const int64_t G = std::max<int64_t>(1, std::min<int64_t>(kMaxPartials, (n + kSelWG - 1) / kSelWG));
         int64_t chunk = (n + G - 1) / G;
@@ -2085,22 +2125,34 @@ int launch_rows_build(const pct_plan &pl, const ProtonsDev &p, int64_t n, int ch
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
-    const double *tab = reinterpret_cast<const double *>(wsb(ws) + L.table);
+    const PathSrc src = path_src(pl, wsb(ws) + L.table);
     unsigned *status = reinterpret_cast<unsigned *>(wsb(ws) + L.hdr) + kHdrStatus;
     const long long *off = reinterpret_cast<const long long *>(offsets);
     const GridDev g = grid_dev(pl.grid);
     switch (chord_type) {
     case PCT_CHORD_F16:
-        hipLaunchKernelGGL(k_rows_build<PCT_CHORD_F16>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
-                           static_cast<unsigned short *>(chord), n2, tab, pl.K, g, status);
+        if (src.hull)
+            hipLaunchKernelGGL((k_rows_build<PCT_CHORD_F16, true>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<unsigned short *>(chord), n2, src, g, status);
+        else
+            hipLaunchKernelGGL((k_rows_build<PCT_CHORD_F16, false>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<unsigned short *>(chord), n2, src, g, status);
         break;
     case PCT_CHORD_BF16:
-        hipLaunchKernelGGL(k_rows_build<PCT_CHORD_BF16>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
-                           static_cast<unsigned short *>(chord), n2, tab, pl.K, g, status);
+        if (src.hull)
+            hipLaunchKernelGGL((k_rows_build<PCT_CHORD_BF16, true>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<unsigned short *>(chord), n2, src, g, status);
+        else
+            hipLaunchKernelGGL((k_rows_build<PCT_CHORD_BF16, false>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<unsigned short *>(chord), n2, src, g, status);
         break;
     default:
-        hipLaunchKernelGGL(k_rows_build<PCT_CHORD_F32>, dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
-                           static_cast<float *>(chord), n2, tab, pl.K, g, status);
+        if (src.hull)
+            hipLaunchKernelGGL((k_rows_build<PCT_CHORD_F32, true>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<float *>(chord), n2, src, g, status);
+        else
+            hipLaunchKernelGGL((k_rows_build<PCT_CHORD_F32, false>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n, off, vox,
+                           static_cast<float *>(chord), n2, src, g, status);
     }
     return hipGetLastError();
 }

@@ -233,17 +233,197 @@ __device__ __forceinline__ void walk_segment(const double P0[3], const double P1
     walk_segment_range(P0, P1, g, 0, 0, g.n[0] - 1, sink);
 }
 
-// Walk of the whole polyline (K segments) of one proton.  `tab` rows are
-// kRowDoubles apart.  Also reports whether the path is monotone along the
-// dominant in-plane axis (needed by the re-entry tracker).
-template <class Sink>
-__device__ __forceinline__ void walk_path(const Rec &r, const double *__restrict__ tab, int K, const GridDev &g,
-                                          Sink &sink)
+// ---------------------------------------------------------------------------
+// Per-proton polyline
+// ---------------------------------------------------------------------------
+// Coefficients of one interior MLP vertex at depth d (mm) of a path of depth D
+// (mm), row layout of the shared table: c0t, c0th (mm), c2t, c2th (mm).  The
+// same mathematics as the host table: scattering matrices by 4-point
+// Gauss-Legendre (exact for the degree-7 integrands) and the Kalman-gain form
+// of the conditional mean, depth of the polynomial measured from the start of
+// the path.
+__device__ __forceinline__ double mlp_poly(const PathSrc &m, double s)
 {
+    double v = 0.0;
+    for (int k = 5; k >= 0; --k) v = v * s + m.poly[k];
+    return v;
+}
+
+__device__ __forceinline__ void mlp_scatter(const PathSrc &m, double lo, double end, double S[4])
+{
+    const double r1 = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    const double r2 = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(6.0 / 5.0));
+    const double w1 = (18.0 + sqrt(30.0)) / 36.0;
+    const double w2 = (18.0 - sqrt(30.0)) / 36.0;
+    const double xs[4] = {-r2, -r1, r1, r2};
+    const double ws[4] = {w2, w1, w1, w2};
+    const double h = 0.5 * (end - lo), c = 0.5 * (end + lo);
+    double J0 = 0.0, J1 = 0.0, J2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double s = c + h * xs[i];
+        const double w = ws[i] * h * mlp_poly(m, s);
+        const double e = end - s;
+        J0 += w;
+        J1 += w * e;
+        J2 += w * e * e;
+    }
+    double f = m.E0 * m.E0 / m.X0;
+    if (m.log_term) {
+        const double l = 1.0 + 0.038 * log((end - lo) / m.X0);
+        f *= l * l;
+    }
+    S[0] = f * J2;
+    S[1] = f * J1;
+    S[2] = f * J1;
+    S[3] = f * J0;
+}
+
+__device__ __forceinline__ void mlp_coeffs(const PathSrc &m, double d_mm, double D_mm, double c[4])
+{
+    const double d = d_mm / 10.0, Dcm = D_mm / 10.0;
+    double S1[4], S2[4];
+    mlp_scatter(m, 0.0, d, S1);
+    mlp_scatter(m, d, Dcm, S2);
+    const double e = Dcm - d;
+    const double a = S1[0] + 2.0 * e * S1[1] + e * e * S1[3] + S2[0];
+    const double bb = S1[1] + e * S1[3] + S2[1];
+    const double dd = S1[3] + S2[3];
+    const double det = a * dd - bb * bb;
+    const double Ti[4] = {dd / det, -bb / det, -bb / det, a / det};
+    const double U[4] = {S1[0] + e * S1[1], S1[1], S1[2] + e * S1[3], S1[3]};
+    const double G0 = U[0] * Ti[0] + U[1] * Ti[2];
+    const double G1 = U[0] * Ti[1] + U[1] * Ti[3];
+    const double q0 = 1.0 - G0;
+    const double q1 = -G0 * e - G1;
+    c[0] = q0;
+    c[1] = (q0 * d + q1) * 10.0;
+    c[2] = G0;
+    c[3] = G1 * 10.0;
+}
+
+// Where a straight track t(u) = t0 + th (u - u0) of gantry angle (cs, sn)
+// crosses the hull circle: the smaller (first = true) or larger root in u.
+__device__ __forceinline__ bool hull_cross(const PathSrc &m, const Rec &r, double t0, double th, double u0,
+                                           bool first, double &u)
+{
+    const double ct = t0 - th * u0;  // t at u = 0
+    const double a1 = r.cs - th * r.sn, b1 = r.sn + th * r.cs;
+    const double a0 = -ct * r.sn - m.hx, b0 = ct * r.cs - m.hy;
+    const double A = a1 * a1 + b1 * b1;
+    const double B = a1 * a0 + b1 * b0;
+    const double C = a0 * a0 + b0 * b0 - m.hr * m.hr;
+    const double disc = B * B - A * C;
+    if (!(disc > 0.0) || !(A > 0.0)) return false;
+    const double q = -(B + copysign(sqrt(disc), B));
+    double x1 = q / A, x2 = C / q;
+    if (q == 0.0) x1 = x2 = -B / A;
+    u = first ? fmin(x1, x2) : fmax(x1, x2);
+    return true;
+}
+
+struct PathState {
+    int nv;         // vertices
+    int pre, kh;    // leading tracker vertex (0/1), MLP segments inside the hull
+    bool miss;      // the tracks do not reach the hull: one straight segment
+    double uh_in, uh_out, t0, v0, t1, v1;
+};
+
+// The hull path is a separate instantiation of the kernels (template flag
+// HULL), so the table path keeps its register allocation.
+__device__ __forceinline__ PathState hull_prepare(const Rec &r, const PathSrc &m)
+{
+    PathState ps{};
+    double u1 = 0.0, u2 = 0.0;
+    const bool hit = hull_cross(m, r, r.t_in, r.th_in, m.u_in, true, u1) &&
+                     hull_cross(m, r, r.t_out, r.th_out, m.u_out, false, u2);
+    ps.uh_in = fmin(fmax(u1, m.u_in), m.u_out);
+    ps.uh_out = fmin(fmax(u2, m.u_in), m.u_out);
+    if (!hit || !(ps.uh_out > ps.uh_in)) {
+        ps.miss = true;
+        ps.nv = 2;
+        return ps;
+    }
+    const double D = ps.uh_out - ps.uh_in;
+    ps.kh = max(1, int(ceil(D / m.step)));
+    ps.pre = ps.uh_in > m.u_in ? 1 : 0;
+    const int post = ps.uh_out < m.u_out ? 1 : 0;
+    ps.nv = ps.pre + ps.kh + 1 + post;
+    ps.t0 = r.t_in + r.th_in * (ps.uh_in - m.u_in);
+    ps.v0 = r.v_in + r.ph_in * (ps.uh_in - m.u_in);
+    ps.t1 = r.t_out + r.th_out * (ps.uh_out - m.u_out);
+    ps.v1 = r.v_out + r.ph_out * (ps.uh_out - m.u_out);
+    return ps;
+}
+
+template <bool HULL>
+__device__ __forceinline__ PathState path_prepare(const Rec &r, const PathSrc &m)
+{
+    if constexpr (HULL) {
+        return hull_prepare(r, m);
+    } else {
+        PathState ps{};
+        ps.nv = m.K + 1;
+        return ps;
+    }
+}
+
+__device__ __forceinline__ void hull_vertex(const Rec &r, const PathSrc &m, const PathState &ps, int k, double *P)
+{
+    double u, t, v;
+    const int j = k - ps.pre;
+    if (ps.miss) {
+        u = k == 0 ? m.u_in : m.u_out;
+        t = k == 0 ? r.t_in : r.t_out;
+        v = k == 0 ? r.v_in : r.v_out;
+    } else if (j < 0) {
+        u = m.u_in;
+        t = r.t_in;
+        v = r.v_in;
+    } else if (j > ps.kh) {
+        u = m.u_out;
+        t = r.t_out;
+        v = r.v_out;
+    } else if (j == 0) {
+        u = ps.uh_in;
+        t = ps.t0;
+        v = ps.v0;
+    } else if (j == ps.kh) {
+        u = ps.uh_out;
+        t = ps.t1;
+        v = ps.v1;
+    } else {
+        const double d = j * m.step;
+        double c[4];
+        mlp_coeffs(m, d, ps.uh_out - ps.uh_in, c);
+        u = ps.uh_in + d;
+        t = c[0] * ps.t0 + c[1] * r.th_in + c[2] * ps.t1 + c[3] * r.th_out;
+        v = c[0] * ps.v0 + c[1] * r.ph_in + c[2] * ps.v1 + c[3] * r.ph_out;
+    }
+    P[0] = u * r.cs - t * r.sn;
+    P[1] = u * r.sn + t * r.cs;
+    P[2] = v;
+}
+
+// Vertex k (0 <= k < ps.nv) in lab coordinates (mm).
+template <bool HULL>
+__device__ __forceinline__ void path_vertex(const Rec &r, const PathSrc &m, const PathState &ps, int k, double P[3])
+{
+    if constexpr (HULL)
+        hull_vertex(r, m, ps, k, P);
+    else
+        vertex(r, m.tab + k * kRowDoubles, P);
+}
+
+// Walk of the whole polyline of one proton.
+template <bool HULL, class Sink>
+__device__ __forceinline__ void walk_path(const Rec &r, const PathSrc &src, const GridDev &g, Sink &sink)
+{
+    const PathState ps = path_prepare<HULL>(r, src);
     double P0[3], P1[3];
-    vertex(r, tab, P0);
-    for (int k = 0; k < K; ++k) {
-        vertex(r, tab + (k + 1) * kRowDoubles, P1);
+    path_vertex<HULL>(r, src, ps, 0, P0);
+    for (int k = 1; k < ps.nv; ++k) {
+        path_vertex<HULL>(r, src, ps, k, P1);
         sink.segment(P1[0] - P0[0], P1[1] - P0[1]);
         walk_segment(P0, P1, g, sink);
         P0[0] = P1[0];

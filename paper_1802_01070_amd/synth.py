@@ -238,6 +238,7 @@ class ScanConfig:
     slab_mm: float = 4.0
     sigma_dir: float = 0.010   # entry slope sigma [rad]
     noise_mm: float = 1.0
+    continuous_angles: bool = False  # gantry angle per proton ~ U[0, 2pi) (drawn last)
 
     def with_(self, **kw) -> "ScanConfig":
         return dataclasses.replace(self, **kw)
@@ -295,6 +296,12 @@ CONFIGS = {
                   block=3200, lam=0.1, n_iter=8, phantom="cyl200", seed=1004),
     5: ScanConfig("cfg5_head256_tvgd", Grid(256, 256, 64), m=20_000_000, n_angles=360, r_hull=110.0,
                   block=6400, lam=0.1, n_iter=20, phantom="head256", order="angle_slab", seed=1005),
+    # continuous gantry rotation (as in the paper's scanner data, Section IV-A)
+    # on the 200x200x32 geometry, protons sorted into 180 angle bins, then by
+    # slab and t_in
+    "cont": ScanConfig("cont_cyl200_anglebins", Grid(200, 200, 32), m=10_000_000, n_angles=180, r_hull=100.0,
+                       block=3200, lam=0.1, n_iter=12, phantom="cyl200", order="angle_slab", seed=1007,
+                       continuous_angles=True),
     # multi-region case: 20 slices like the reconstructions of the paper's
     # Section II example (two regions, slices 0-12 and 7-19)
     "regions": ScanConfig("regions_cyl64x20", Grid(64, 64, 20), m=60_000, n_angles=90, r_hull=30.0, block=3200,
@@ -391,9 +398,12 @@ def make_scan(cfg: ScanConfig, m: Optional[int] = None, seed: Optional[int] = No
         th_out = th_in + (chol[1, 0] * zt[:, 0] + chol[1, 1] * zt[:, 1])
         v_out = v_in + ph_in * D + (chol[0, 0] * zv[:, 0] + chol[0, 1] * zv[:, 1])
         ph_out = ph_in + (chol[1, 0] * zv[:, 0] + chol[1, 1] * zv[:, 1])
-        idx = np.arange(lo, hi, dtype=np.int64)
-        ang = (idx * cfg.n_angles) // m
-        phi = (2.0 * np.pi * ang / cfg.n_angles).astype(np.float32)
+        if cfg.continuous_angles:
+            phi = rng.uniform(0.0, 2.0 * np.pi, n).astype(np.float32)
+        else:
+            idx = np.arange(lo, hi, dtype=np.int64)
+            ang = (idx * cfg.n_angles) // m
+            phi = (2.0 * np.pi * ang / cfg.n_angles).astype(np.float32)
         rec = dict(t_in=t_in, v_in=v_in, th_in=th_in, ph_in=ph_in, t_out=t_out, v_out=v_out,
                    th_out=th_out, ph_out=ph_out)
         for k, v in rec.items():

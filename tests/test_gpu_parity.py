@@ -263,6 +263,7 @@ def test_drop_config1_fp64_full(lanes):
 
 
 @pytest.mark.parametrize("cfg,m,iters,lanes", [(2, 64000, 2, 0), (2, 64000, 2, 1), (2, 64000, 2, 16),
+                                               ("cont", 64000, 2, 0),
                                                (3, 64000, 1, 0), (3, 64000, 1, 32)])
 def test_drop_fp32(cfg, m, iters, lanes):
     c = synth.CONFIGS[cfg]
