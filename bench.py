@@ -92,12 +92,13 @@ def count_nonzeros(api, plan, pr, chunk=1 << 20):
     return total
 
 
-def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks):
+def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks, hull=0.0):
     """FP64 oracle on the first n_blocks blocks of one sweep (from x0 = 1):
     throughput on the host cores and the RSP error of the GPU result on the
     same sample."""
     import oracle
     oracle.build(force=False)
+    oracle.set_hull(hull or None)
     m = min(sc.m, n_blocks * cfg.block)
     sub = sc.subset(0, m)
     t0 = time.perf_counter()
@@ -429,6 +430,8 @@ def main():
     ap.add_argument("--protons", type=int, default=0, help="override the number of protons")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-order", action="store_true", help="keep the acquisition order inside blocks")
+    ap.add_argument("--hull", type=float, default=0.0,
+                    help="radius (mm) of a z-cylinder object hull: per-proton paths between the hull crossings")
     ap.add_argument("--cpu-blocks", type=int, default=320)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per proton in the block kernel (0: automatic)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -461,6 +464,8 @@ def main():
     log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
     dev = "cuda:0"
     plan = api.Plan(sc.grid, sc.mlp, dev)
+    if args.hull > 0:
+        plan.set_hull(args.hull)
     pr = api.Protons(sc.protons, dev)
     b = torch.from_numpy(sc.b).to(dev)
     vdtype = torch.float64 if cfg.value_type == "f64" else torch.float32
@@ -539,7 +544,8 @@ def main():
                                         "block t, commit of block t-1)")
     else:
         kname, kdesc = "k_drop_block", "k_drop_block (MLP trace + a.x + |a|^2 + rho + scatter) + k_drop_commit"
-    traffic, traffic_src = measured_traffic(cfg.name, kname) if not args.protons else (None, "non-default size")
+    traffic, traffic_src = (measured_traffic(cfg.name, kname) if not (args.protons or args.hull)
+                            else (None, "counters taken on the default tracker-to-tracker run"))
 
     out = {
         "metric": "proton-iterations/sec (fused MLP+DROP) at 1 GPU",
@@ -562,6 +568,7 @@ def main():
             "protons": m, "block": cfg.block, "lambda": cfg.lam, "grid": [sc.grid.nx, sc.grid.ny, sc.grid.nz],
             "nonzeros_per_proton": sum_nnz / m, "blocks_per_sweep": T,
             "order_inside_blocks": "acquisition" if order_ms is None else "entry slice, t_in (pct_order_blocks)",
+            "hull_radius_mm": args.hull or None,
             "order_ms_once": order_ms,
         },
         "roofline": {
@@ -592,7 +599,7 @@ def main():
         api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1, block_end=nb, lanes=args.lanes)
         torch.cuda.synchronize()
         log(f"[bench] CPU oracle baseline on {nb} blocks ...")
-        cb, emax, emean = cpu_baseline(sc, cfg, xs.double().cpu().numpy(), nb)
+        cb, emax, emean = cpu_baseline(sc, cfg, xs.double().cpu().numpy(), nb, args.hull)
         out["cpu_baseline"] = cb
         out["rsp_err_vs_fp64_oracle"] = {"sample": f"first {nb} blocks of one sweep", "max": emax, "mean": emean}
     if args.calib_copy_mib:

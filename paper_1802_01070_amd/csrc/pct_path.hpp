@@ -56,7 +56,6 @@ __device__ __forceinline__ void vertex(const Rec &r, const double *__restrict__ 
     P[2] = v;
 }
 
-
 // Walk of one straight segment P0 -> P1 through the part of the grid whose
 // index along axis `ra` lies in [r_lo, r_hi] (Siddon's parametrisation
 // P0 + alpha (P1 - P0), alpha in [0, 1]).  Calls sink.piece(ix, iy, iz, chord)
@@ -90,7 +89,10 @@ __device__ __forceinline__ void walk_segment_range(const double P0[3], const dou
             double t0 = (lo[a] - P0[a]) * inv[a];
             double t1 = (hi[a] - P0[a]) * inv[a];
             a_lo = fmax(a_lo, fmin(t0, t1));
-            a_hi = fmin(a_hi, fmax(t0, t1));
+            // d * inv is the parameter a plane through the end point gets
+            // below; it may round under 1, and the walk must stop there, not
+            // step into the next voxel for a piece of rounding length
+            a_hi = fmin(a_hi, fmin(fmax(t0, t1), d[a] * inv[a]));
         } else {
             inv[a] = 0.0;
             if (!(P0[a] >= lo[a] && P0[a] < hi[a])) a_hi = -1.0;
@@ -136,90 +138,6 @@ __device__ __forceinline__ void walk_segment_range(const double P0[3], const dou
                 out |= (i < ilo[a]) | (i > ihi[a]);
                 idx[a] = i;
                 anext[a] = (g.lo[a] + (i + (stp[a] > 0 ? 1 : 0)) * g.pitch[a] - P0[a]) * inv[a];
-            }
-        }
-        if (out) break;
-        acur = fmax(acur, am);
-    }
-}
-
-// Walk of the part of segment P0 -> P1 inside dominant-axis slab `s` (index
-// range [s, s] along axis `da`), given the segment's precomputed inverse
-// direction `inv` and length `len`.  Along the dominant axis the slab faces are
-// the only crossings, so the walk steps through the two other axes only.  The
-// crossing parameters are the same expressions as in walk_segment_range, so
-// the pieces are exactly the pieces of the full walk that fall in the slab.
-template <class Sink>
-__device__ __forceinline__ void walk_segment_slab(const double *__restrict__ P0, const double *__restrict__ P1,
-                                                  const double *__restrict__ inv, double len, const GridDev &g,
-                                                  int da, int s, Sink &sink)
-{
-    const int b0 = da == 0 ? 1 : 0;  // the two other axes: b0 < b1, z last
-    const int ax[2] = {b0, 2};
-    double a_lo = 0.0, a_hi = 1.0;
-    // slab faces along the dominant axis (the path is monotone, d != 0)
-    {
-        const double t0 = (g.lo[da] + s * g.pitch[da] - P0[da]) * inv[da];
-        const double t1 = (g.lo[da] + (s + 1) * g.pitch[da] - P0[da]) * inv[da];
-        a_lo = fmax(a_lo, fmin(t0, t1));
-        a_hi = fmin(a_hi, fmax(t0, t1));
-    }
-    double d[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) d[a] = P1[a] - P0[a];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int a = ax[q];
-        if (d[a] != 0.0) {
-            const double t0 = (g.lo[a] - P0[a]) * inv[a];
-            const double t1 = (g.hi[a] - P0[a]) * inv[a];
-            a_lo = fmax(a_lo, fmin(t0, t1));
-            a_hi = fmin(a_hi, fmax(t0, t1));
-        } else if (!(P0[a] >= g.lo[a] && P0[a] < g.hi[a])) {
-            a_hi = -1.0;
-        }
-    }
-    if (!(a_lo < a_hi)) return;
-    int idx[3], stp[2];
-    double anext[2];
-    idx[da] = s;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int a = ax[q];
-        const double pos = P0[a] + a_lo * d[a];
-        const double qq = (pos - g.lo[a]) * g.inv_pitch[a];
-        const double f = floor(qq);
-        int i = int(fmin(fmax(f, -1.0), double(g.n[a])));
-        if (d[a] < 0.0 && f == qq) i -= 1;  // on a plane and moving down
-        i = min(max(i, 0), g.n[a] - 1);
-        idx[a] = i;
-        if (d[a] > 0.0) {
-            stp[q] = 1;
-            anext[q] = (g.lo[a] + (i + 1) * g.pitch[a] - P0[a]) * inv[a];
-        } else if (d[a] < 0.0) {
-            stp[q] = -1;
-            anext[q] = (g.lo[a] + i * g.pitch[a] - P0[a]) * inv[a];
-        } else {
-            stp[q] = 0;
-            anext[q] = 2.0;
-        }
-    }
-    double acur = a_lo;
-    const int max_it = g.n[0] + g.n[1] + g.n[2] + 4;
-    for (int it = 0; it < max_it; ++it) {
-        const double am = fmin(anext[0], anext[1]);
-        const double aend = fmin(am, a_hi);
-        if (aend > acur) sink.piece(idx[0], idx[1], idx[2], (aend - acur) * len);
-        if (!(am < a_hi)) break;
-        bool out = false;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            if (anext[q] == am) {
-                const int a = ax[q];
-                const int i = idx[a] + stp[q];
-                out |= (i < 0) | (i >= g.n[a]);
-                idx[a] = i;
-                anext[q] = (g.lo[a] + (i + (stp[q] > 0 ? 1 : 0)) * g.pitch[a] - P0[a]) * inv[a];
             }
         }
         if (out) break;
