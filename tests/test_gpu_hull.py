@@ -166,9 +166,9 @@ def test_drop_rows_ending_on_a_grid_plane(radius):
         plan.set_hull(radius)
     oracle.set_hull(radius)
     pr = api.Protons(protons, DEV)
-    _, _, nnz = api.pct_mlp_trace(plan, pr, 0, n, max_nnz=1)
+    _, _, nnz = api.pct_mlp_trace(plan, pr, 0, n, max_nnz=128)
     _, _, rn = oracle.trace(grid, mlp, protons, cap=1)
-    assert np.array_equal(nnz.cpu().numpy(), rn)
+    assert rn.max() <= 128 and np.array_equal(nnz.cpu().numpy(), rn)
     ref = oracle.drop(grid, mlp, protons, b, 1.0, block=64, lam=0.5, n_iter=2)
     for lanes in (64, 1):
         x = torch.ones(grid.nvox, dtype=torch.float64, device=DEV)
