@@ -421,6 +421,99 @@ def run_regions(args):
     print(json.dumps(out), flush=True)
 
 
+FBP_FLOPS_PER_VOXEL_ANGLE = 12.0   # t (2 mul, 1 add), s (1 sub, 1 mul, 1 sub), w (1 sub), value (1 sub, 2 mul, 1 add), sum (1 add)
+FBP_BIN_BYTES_PER_PROTON = 36.0    # t_in, t_out, v_in, v_out, gantry, b (24 B) + bin sum and count update (12 B)
+
+
+def run_fbp(args):
+    """FBP initial iterate (Section I) on the 10^7-proton scan: time of the
+    image (binning, ramp filter, back-projection), its kernels, and DROP
+    sweeps started from it against x0 = 1."""
+    import torch
+    from paper_1802_01070_amd import api, synth
+    cfg = synth.CONFIGS[2]
+    m = args.protons or cfg.m
+    log(f"[bench] generating {cfg.name}: {m} protons")
+    t0 = time.perf_counter()
+    sc = synth.make_scan(cfg, m=m)
+    log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
+    dev = "cuda:0"
+    plan = api.Plan(sc.grid, sc.mlp, dev)
+    pr = api.Protons(sc.protons, dev)
+    b = torch.from_numpy(sc.b).to(dev)
+    geom = api.FbpGeom.for_grid(sc.grid, cfg.n_angles)
+    ws = api.FbpWorkspace(plan, geom)
+    x = torch.empty(sc.grid.nvox, dtype=torch.float32, device=dev)
+    for _ in range(max(1, args.warmup)):
+        api.pct_fbp(plan, pr, b, geom, x=x, ws=ws)
+    steps = args.steps
+    ms = time_events(lambda: api.pct_fbp(plan, pr, b, geom, x=x, ws=ws), reps=steps) / 1.0
+    # the three steps on their own (HIP events on the stream they run on)
+    box = {}
+    t_sino = time_events(lambda: box.__setitem__("s", api.pct_fbp_sinogram(plan, pr, b, geom, ws=ws)), reps=3)
+    t_filt = time_events(lambda: box.__setitem__("q", api.pct_fbp_filter(plan, box["s"][0], geom)), reps=3)
+    t_bp = time_events(lambda: box.__setitem__("x", api.pct_fbp_backproject(plan, box["q"], geom)), reps=3)
+    nb = sc.grid.nz * geom.n_angles * geom.n_t
+    log(f"[bench] FBP image {ms:.3f} ms (sinogram {t_sino:.3f}, filter {t_filt:.3f}, back-projection {t_bp:.3f})")
+    bp_flops = float(sc.grid.nvox) * geom.n_angles * FBP_FLOPS_PER_VOXEL_ANGLE
+    bin_bytes = FBP_BIN_BYTES_PER_PROTON * m
+    stages = {"sinogram_ms": t_sino, "filter_ms": t_filt, "backproject_ms": t_bp}
+    if t_bp >= t_sino:
+        roof = {"bound": "alu", "achieved": bp_flops / (t_bp * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                "kernel": "k_fbp_backproject (FP64 vector ALU)", "kernel_avg_us": 1e3 * t_bp,
+                "algorithmic_flops_per_launch": bp_flops}
+    else:
+        roof = {"bound": "hbm", "achieved": bin_bytes / (t_sino * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "kernel": "k_fbp_clear + k_fbp_bin + k_fbp_mean", "kernel_avg_us": 1e3 * t_sino,
+                "algorithmic_bytes_per_launch": bin_bytes}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    # DROP from x0 = 1 and from the FBP image
+    n_sweeps = 6
+    runs = {}
+    for name in ("x0_one", "x0_fbp"):
+        xs = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
+        api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1)      # warm-up (graph)
+        if name == "x0_one":
+            xs.fill_(1.0)
+        else:
+            api.pct_fbp(plan, pr, b, geom, x=xs, ws=ws)
+        sweeps = [{"sweep": 0, "inserts": insert_errors(sc, xs)}]
+        for k in range(n_sweeps):
+            t = time_events(lambda: api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1))
+            sweeps.append({"sweep": k + 1, "ms": t, "inserts": insert_errors(sc, xs)})
+        runs[name] = sweeps
+        worst = [max(abs(i["err_pct"]) for i in s["inserts"]) for s in sweeps]
+        log(f"[bench] DROP from {name}: worst insert error per sweep {[round(w, 2) for w in worst]} %")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import fbp as ofbp
+        log("[bench] CPU oracle FBP ...")
+        t0 = time.perf_counter()
+        rp, _ = ofbp.sinogram(sc.grid, sc.mlp, sc.protons, sc.b, geom.n_angles, geom.n_t, geom.t0, geom.dt)
+        rx = ofbp.backproject(sc.grid, ofbp.filter_rows(rp, geom.dt), geom.n_angles, geom.t0, geom.dt)
+        t_cpu = time.perf_counter() - t0
+        err = float(np.abs(x.double().cpu().numpy() - rx).max() / max(1.0, np.abs(rx).max()))
+        cpu = {"value": m / t_cpu, "unit": "protons/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole FBP image of the same scan (numpy FP64, one thread), {t_cpu:.1f} s",
+               "max_rel_err_gpu_vs_oracle": err}
+    out = {
+        "metric": "protons/s into the FBP initial image (binning, ramp filter, back-projection) at 1 GPU",
+        "value": m / (ms * 1e-3), "unit": "protons/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {sc.grid.nx}x{sc.grid.ny}x{sc.grid.nz} grid, {m} protons, "
+                               f"FBP with {geom.n_angles} angle bins x {geom.n_t} lateral bins of {geom.dt} mm x "
+                               f"{sc.grid.nz} slices ({nb} bins), FP32 image",
+                   "geom": {"n_angles": geom.n_angles, "n_t": geom.n_t, "t0": geom.t0, "dt": geom.dt}},
+        "stages": stages,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "drop_from_x0": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -455,6 +548,8 @@ def main():
         return run_regions(args)
     if args.config == "bsweep":
         return run_block_sizes(args)
+    if args.config == "fbp":
+        return run_fbp(args)
     key = int(args.config) if args.config.isdigit() else args.config
     cfg = synth.CONFIGS[key]
     m = args.protons or cfg.m

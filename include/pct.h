@@ -338,6 +338,61 @@ int pct_slice_span_histogram(const pct_plan *plan, const pct_protons *p, int64_t
 int pct_select_slices(const pct_plan *plan, const void *src, int32_t src_z0, void *dst, int32_t dst_z0,
                       int32_t z_first, int32_t z_count, int32_t dtype, void *stream);
 
+/* ---- FBP initial iterate (Section I) --------------------------------------
+ * The iterative solve starts from a filtered back-projection (FBP) image.  The
+ * paper does not print its FBP; this library implements parallel-beam FBP
+ * slice by slice along each proton's straight entry-to-exit chord (Kak &
+ * Slaney, Principles of Computerized Tomographic Imaging, ch. 3):
+ *   binning  -- proton i goes to angle bin a = floor(phi / dphi + 1/2) mod
+ *               n_angles (dphi = 2 pi / n_angles), lateral bin
+ *               k = floor((t_c - t0) / dt) and the slice iz of the plan's grid
+ *               holding v_c, (t_c, v_c) being the chord at depth u = 0:
+ *               t_c = t_in + w (t_out - t_in), w = -u_in / (u_out - u_in), same
+ *               for v.  Protons outside the bins, with a non-finite field or b,
+ *               or with |b| >= 2^20 mm are dropped.  The projection of a bin
+ *               is the mean b of its protons, 0 for an empty bin.  Sums are
+ *               accumulated in 2^-24 mm fixed point (order-independent);
+ *               a bin's sum of |b| must stay below 2^39 mm.
+ *   filter   -- Ram-Lak ramp filter along t as a direct convolution over the
+ *               row, zero beyond it: q_k = dt sum_n p_n h(k - n), h(0) =
+ *               1/(4 dt^2), h(m) = -1/(pi^2 m^2 dt^2) for odd m, 0 otherwise.
+ *   back-projection -- x at a voxel centre (x, y) of slice iz =
+ *               (pi / n_angles) sum_a q_{iz,a}(t), t = -x sin(a dphi) +
+ *               y cos(a dphi), linear interpolation between the lateral bin
+ *               centres t0 + (k + 1/2) dt, zero beyond the outer bins.
+ * The plan's hull setting does not apply (chords are straight).  Sinograms
+ * are device double arrays laid out [iz][a][k] (nz * n_angles * n_t values).
+ * Limits: 1 <= n_angles <= 4096, 1 <= n_t <= 4096, nz * n_angles * n_t <
+ * 2^31, dt > 0 and t0 finite (PCT_ERR_INVALID_ARG otherwise). */
+typedef struct {
+    int32_t n_angles; /* angle bins over the full turn                           */
+    int32_t n_t;      /* lateral bins                                            */
+    double t0, dt;    /* lateral bin k covers [t0 + k dt, t0 + (k+1) dt) (mm)     */
+} pct_fbp_geom;
+
+/* Bytes of the FBP workspace (device memory owned by the caller, no upload
+ * needed): per bin an int64 sum, a uint32 count and two doubles. */
+int pct_fbp_workspace_size(const pct_plan *plan, const pct_fbp_geom *geom, size_t *bytes);
+
+/* Binning: proj (double[nbins]) receives the mean b per bin and count
+ * (int32[nbins], may be NULL) the number of protons in it.  b: float[n].
+ * Uses the sum and count parts of the FBP workspace. */
+int pct_fbp_sinogram(const pct_plan *plan, const pct_fbp_geom *geom, const pct_protons *p, const float *b,
+                     double *proj, int32_t *count, void *fbp_ws, size_t fbp_ws_bytes, void *stream);
+
+/* Ramp filter of every row: q (double[nbins]) from proj; the arrays must not
+ * overlap. */
+int pct_fbp_filter(const pct_plan *plan, const pct_fbp_geom *geom, const double *proj, double *q, void *stream);
+
+/* Back-projection: x (dtype[nvox], overwritten) from the filtered rows q. */
+int pct_fbp_backproject(const pct_plan *plan, const pct_fbp_geom *geom, const double *q, void *x, int32_t dtype,
+                        void *stream);
+
+/* The three steps: x (dtype[nvox], overwritten) = FBP image of (p, b); the
+ * sinograms live in the FBP workspace. */
+int pct_fbp(const pct_plan *plan, const pct_fbp_geom *geom, const pct_protons *p, const float *b, void *x,
+            int32_t dtype, void *fbp_ws, size_t fbp_ws_bytes, void *stream);
+
 /* ---- diagnostics --------------------------------------------------------- */
 
 /* Kernel timing of the last pct_drop_iterate call made with PCT_DROP_PROFILE:

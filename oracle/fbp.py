@@ -15,9 +15,9 @@ binning
     (dphi = 2 pi / n_angles), lateral bin k = floor((t_c - t0) / dt) and the
     slice iz of the grid holding v_c, where (t_c, v_c) is the chord at depth
     u = 0: w = -u_in / (u_out - u_in), t_c = t_in + w (t_out - t_in), same for
-    v.  Protons outside the bins, or with a non-finite field or b, are
-    dropped.  The projection of a bin is the mean b of its protons (0 when it
-    is empty).
+    v.  Protons outside the bins, with a non-finite field or b, or with
+    |b| >= 2^20 mm (not a WEPL), are dropped.  The projection of a bin is the
+    mean b of its protons (0 when it is empty).
 filter
     ramp (Ram-Lak) filter along t, as a plain convolution over the row with
     zeros beyond it: q_k = dt sum_n p_n h(k - n), h(0) = 1/(4 dt^2),
@@ -49,7 +49,7 @@ def bins(grid, mlp, protons: dict, b, n_angles: int, n_t: int, t0: float, dt: fl
     phi = np.asarray(protons["gantry"], dtype=np.float64)
     bb = np.asarray(b, dtype=np.float64)
     dphi = 2.0 * np.pi / n_angles
-    ok = np.isfinite(tc) & np.isfinite(vc) & np.isfinite(phi) & np.isfinite(bb)
+    ok = np.isfinite(tc) & np.isfinite(vc) & np.isfinite(phi) & np.isfinite(bb) & (np.abs(bb) < 2.0 ** 20)
     with np.errstate(invalid="ignore"):
         fa = np.floor(phi / dphi + 0.5)
         fk = np.floor((tc - float(t0)) / float(dt))

@@ -28,7 +28,8 @@ EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan
            "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read",
            "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
            "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows",
-           "pct_order_blocks", "pct_plan_set_hull")
+           "pct_order_blocks", "pct_plan_set_hull", "pct_fbp_workspace_size", "pct_fbp_sinogram", "pct_fbp_filter",
+           "pct_fbp_backproject", "pct_fbp")
 
 
 class PctError(RuntimeError):
@@ -62,6 +63,10 @@ class pct_protons_buf(C.Structure):
 class pct_rows(C.Structure):
     _fields_ = [("offsets", C.c_void_p), ("vox", C.c_void_p), ("chord", C.c_void_p), ("n2", C.c_void_p),
                 ("n", C.c_int64), ("chord_type", C.c_int32), ("reserved", C.c_int32)]
+
+
+class pct_fbp_geom(C.Structure):
+    _fields_ = [("n_angles", C.c_int32), ("n_t", C.c_int32), ("t0", C.c_double), ("dt", C.c_double)]
 
 
 class pct_drop_opts(C.Structure):
@@ -108,6 +113,11 @@ def lib() -> C.CDLL:
             "pct_plan_set_hull": ([vp, P(pct_hull)], C.c_int),
             "pct_rows_build": ([vp, P(pct_protons), i32, vp, vp, vp, vp, vp, sz, vp], C.c_int),
             "pct_drop_iterate_rows": ([vp, P(pct_rows), vp, vp, P(pct_drop_opts), vp, sz, vp], C.c_int),
+            "pct_fbp_workspace_size": ([vp, P(pct_fbp_geom), P(sz)], C.c_int),
+            "pct_fbp_sinogram": ([vp, P(pct_fbp_geom), P(pct_protons), vp, vp, vp, vp, sz, vp], C.c_int),
+            "pct_fbp_filter": ([vp, P(pct_fbp_geom), vp, vp, vp], C.c_int),
+            "pct_fbp_backproject": ([vp, P(pct_fbp_geom), vp, vp, i32, vp], C.c_int),
+            "pct_fbp": ([vp, P(pct_fbp_geom), P(pct_protons), vp, vp, i32, vp, sz, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

@@ -7,8 +7,10 @@ shapes/dtypes/devices, marshals pointers and calls libpct.
 from __future__ import annotations
 
 import ctypes as C
+from dataclasses import dataclass
 from typing import Optional
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -385,6 +387,87 @@ def region_drop(plan: Plan, p: Protons, b: torch.Tensor, x: torch.Tensor, n_regi
         z_lo, _, c_lo, c_hi = reg["layout"]
         pct_select_slices(plan, reg["x"], z_lo, x, 0, c_lo, c_hi - c_lo + 1)
     return regions
+
+
+@dataclass(frozen=True)
+class FbpGeom:
+    """Bins of the FBP initial iterate: n_angles angle bins over the full turn
+    and n_t lateral bins [t0 + k dt, t0 + (k+1) dt) (mm); the slices of the
+    plan's grid are the third axis."""
+    n_angles: int
+    n_t: int
+    t0: float
+    dt: float
+
+    @staticmethod
+    def for_grid(grid, n_angles: int, dt: Optional[float] = None) -> "FbpGeom":
+        """Lateral bins of the voxel pitch covering the grid's diagonal,
+        centred on the rotation axis."""
+        dt = float(dt if dt is not None else min(grid.pitch[0], grid.pitch[1]))
+        half = 0.5 * float(np.hypot(grid.nx * grid.pitch[0], grid.ny * grid.pitch[1]))
+        n_t = 2 * int(np.ceil(half / dt))
+        return FbpGeom(int(n_angles), n_t, -0.5 * n_t * dt, dt)
+
+    def struct(self):
+        return _lib.pct_fbp_geom(int(self.n_angles), int(self.n_t), float(self.t0), float(self.dt))
+
+
+class FbpWorkspace:
+    """Device scratch of the FBP entry points (256-byte aligned)."""
+
+    def __init__(self, plan: Plan, geom: FbpGeom, device=None):
+        nbytes = C.c_size_t()
+        check(lib().pct_fbp_workspace_size(plan.handle, C.byref(geom.struct()), C.byref(nbytes)),
+              "pct_fbp_workspace_size")
+        self.nbytes = int(nbytes.value)
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device or plan.device)
+        self.ptr = C.c_void_p(self.buf.data_ptr() + (-self.buf.data_ptr()) % 256)
+
+
+def pct_fbp_sinogram(plan: Plan, p: Protons, b: torch.Tensor, geom: FbpGeom, ws: Optional[FbpWorkspace] = None):
+    """Mean WEPL and proton count per (slice, angle, lateral) bin."""
+    dev = b.device
+    bp = _dev(b, "b", dtype=torch.float32, numel=p.n)
+    shape = (plan.grid.nz, geom.n_angles, geom.n_t)
+    proj = torch.empty(shape, dtype=torch.float64, device=dev)
+    count = torch.empty(shape, dtype=torch.int32, device=dev)
+    ws = FbpWorkspace(plan, geom, dev) if ws is None else ws
+    st = lib().pct_fbp_sinogram(plan.handle, C.byref(geom.struct()), C.byref(p.s), bp, proj.data_ptr(),
+                                count.data_ptr(), ws.ptr, ws.nbytes, _stream(dev))
+    check(st, "pct_fbp_sinogram")
+    return proj, count
+
+
+def pct_fbp_filter(plan: Plan, proj: torch.Tensor, geom: FbpGeom):
+    """Ram-Lak filtered rows of a sinogram."""
+    pp = _dev(proj, "proj", dtype=torch.float64, numel=plan.grid.nz * geom.n_angles * geom.n_t)
+    q = torch.empty_like(proj)
+    check(lib().pct_fbp_filter(plan.handle, C.byref(geom.struct()), pp, q.data_ptr(), _stream(proj.device)),
+          "pct_fbp_filter")
+    return q
+
+
+def pct_fbp_backproject(plan: Plan, q: torch.Tensor, geom: FbpGeom, dtype=torch.float32):
+    """FBP image (flat voxel order) from filtered rows."""
+    qp = _dev(q, "q", dtype=torch.float64, numel=plan.grid.nz * geom.n_angles * geom.n_t)
+    x = torch.empty(plan.nvox, dtype=dtype, device=q.device)
+    check(lib().pct_fbp_backproject(plan.handle, C.byref(geom.struct()), qp, x.data_ptr(), _dtype_code(x),
+                                    _stream(q.device)), "pct_fbp_backproject")
+    return x
+
+
+def pct_fbp(plan: Plan, p: Protons, b: torch.Tensor, geom: FbpGeom, dtype=torch.float32,
+            x: Optional[torch.Tensor] = None, ws: Optional[FbpWorkspace] = None):
+    """FBP image of the protons: the initial iterate of the DROP solve."""
+    dev = b.device
+    bp = _dev(b, "b", dtype=torch.float32, numel=p.n)
+    x = torch.empty(plan.nvox, dtype=dtype, device=dev) if x is None else x
+    xp = _dev(x, "x", numel=plan.nvox)
+    ws = FbpWorkspace(plan, geom, dev) if ws is None else ws
+    st = lib().pct_fbp(plan.handle, C.byref(geom.struct()), C.byref(p.s), bp, xp, _dtype_code(x), ws.ptr,
+                       ws.nbytes, _stream(dev))
+    check(st, "pct_fbp")
+    return x
 
 
 class DropSolver:

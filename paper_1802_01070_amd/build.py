@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpct.so")
-SOURCES = ["pct_api.cpp", "pct_kernels.hip"]
+SOURCES = ["pct_api.cpp", "pct_kernels.hip", "pct_fbp.hip"]
 HEADERS = ["pct_internal.h", "pct_path.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

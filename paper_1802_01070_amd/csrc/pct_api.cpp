@@ -233,6 +233,50 @@ static int check_ws(const pct_plan *pl, void *ws, size_t ws_bytes, int dtype)
 
 static bool valid_dtype(int32_t d) { return d == PCT_F32 || d == PCT_F64; }
 
+FbpLayout fbp_layout(int64_t nbins)
+{
+    FbpLayout L{};
+    size_t off = 0;
+    L.sum = off;
+    off = align256(off + size_t(nbins) * sizeof(uint64_t));
+    L.cnt = off;
+    off = align256(off + size_t(nbins) * sizeof(uint32_t));
+    L.proj = off;
+    off = align256(off + size_t(nbins) * sizeof(double));
+    L.q = off;
+    off = align256(off + size_t(nbins) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+// Validated FBP geometry of a plan; nbins receives nz * n_angles * n_t.
+static int fbp_geometry(const pct_plan *plan, const pct_fbp_geom *geom, FbpDev &f, int64_t &nbins)
+{
+    if (!plan || !geom) return PCT_ERR_INVALID_ARG;
+    if (geom->n_angles < 1 || geom->n_angles > kFbpMaxAngles) return PCT_ERR_INVALID_ARG;
+    if (geom->n_t < 1 || geom->n_t > kFbpMaxLateral) return PCT_ERR_INVALID_ARG;
+    if (!std::isfinite(geom->t0) || !finite_pos(geom->dt)) return PCT_ERR_INVALID_ARG;
+    nbins = int64_t(plan->grid.nz) * geom->n_angles * geom->n_t;
+    if (nbins >= (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
+    f = FbpDev{};
+    f.n_ang = geom->n_angles;
+    f.n_t = geom->n_t;
+    f.nz = plan->grid.nz;
+    f.t0 = geom->t0;
+    f.dt = geom->dt;
+    f.dphi = 2.0 * M_PI / geom->n_angles;
+    f.w = -plan->mlp.u_in / (plan->mlp.u_out - plan->mlp.u_in);
+    f.z0 = plan->grid.origin[2];
+    f.pz = plan->grid.pitch[2];
+    return PCT_OK;
+}
+
+static bool disjoint(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa + na <= pb || pb + nb <= pa;
+}
+
 }  // namespace pct
 
 using namespace pct;
@@ -564,6 +608,84 @@ int pct_select_slices(const pct_plan *plan, const void *src, int32_t src_z0, voi
     const char *s = static_cast<const char *>(src) + size_t(z_first - src_z0) * plane;
     char *d = static_cast<char *>(dst) + size_t(z_first - dst_z0) * plane;
     return hip_status(copy_device(d, s, size_t(z_count) * plane, stream));
+}
+
+int pct_fbp_workspace_size(const pct_plan *plan, const pct_fbp_geom *geom, size_t *bytes)
+{
+    FbpDev f;
+    int64_t nb;
+    int st = fbp_geometry(plan, geom, f, nb);
+    if (st) return st;
+    if (!bytes) return PCT_ERR_INVALID_ARG;
+    *bytes = fbp_layout(nb).total;
+    return PCT_OK;
+}
+
+int pct_fbp_sinogram(const pct_plan *plan, const pct_fbp_geom *geom, const pct_protons *p, const float *b,
+                     double *proj, int32_t *count, void *fbp_ws, size_t fbp_ws_bytes, void *stream)
+{
+    FbpDev f;
+    int64_t nb;
+    int st = fbp_geometry(plan, geom, f, nb);
+    if (st) return st;
+    st = check_protons(p);
+    if (st) return st;
+    if (!proj || (p->n > 0 && !b)) return PCT_ERR_INVALID_ARG;
+    const FbpLayout L = fbp_layout(nb);
+    if (!fbp_ws || fbp_ws_bytes < L.proj || (reinterpret_cast<uintptr_t>(fbp_ws) & 255u)) return PCT_ERR_WORKSPACE;
+    char *w = static_cast<char *>(fbp_ws);
+    if (!disjoint(proj, size_t(nb) * 8, w, L.proj) || (count && !disjoint(count, size_t(nb) * 4, w, L.proj)))
+        return PCT_ERR_INVALID_ARG;
+    return hip_status(launch_fbp_sinogram(f, protons_dev(p), p->n, b, reinterpret_cast<unsigned long long *>(w + L.sum),
+                                          reinterpret_cast<unsigned *>(w + L.cnt), proj, count, stream));
+}
+
+int pct_fbp_filter(const pct_plan *plan, const pct_fbp_geom *geom, const double *proj, double *q, void *stream)
+{
+    FbpDev f;
+    int64_t nb;
+    int st = fbp_geometry(plan, geom, f, nb);
+    if (st) return st;
+    if (!proj || !q || !disjoint(proj, size_t(nb) * 8, q, size_t(nb) * 8)) return PCT_ERR_INVALID_ARG;
+    return hip_status(launch_fbp_filter(f, proj, q, stream));
+}
+
+int pct_fbp_backproject(const pct_plan *plan, const pct_fbp_geom *geom, const double *q, void *x, int32_t dtype,
+                        void *stream)
+{
+    FbpDev f;
+    int64_t nb;
+    int st = fbp_geometry(plan, geom, f, nb);
+    if (st) return st;
+    if (!q || !x || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
+    const size_t xb = size_t(plan->nvox) * (dtype == PCT_F64 ? 8 : 4);
+    if (!disjoint(q, size_t(nb) * 8, x, xb)) return PCT_ERR_INVALID_ARG;
+    return hip_status(launch_fbp_backproject(f, grid_dev(plan->grid), q, x, dtype, stream));
+}
+
+int pct_fbp(const pct_plan *plan, const pct_fbp_geom *geom, const pct_protons *p, const float *b, void *x,
+            int32_t dtype, void *fbp_ws, size_t fbp_ws_bytes, void *stream)
+{
+    FbpDev f;
+    int64_t nb;
+    int st = fbp_geometry(plan, geom, f, nb);
+    if (st) return st;
+    st = check_protons(p);
+    if (st) return st;
+    if (!x || !valid_dtype(dtype) || (p->n > 0 && !b)) return PCT_ERR_INVALID_ARG;
+    const FbpLayout L = fbp_layout(nb);
+    if (!fbp_ws || fbp_ws_bytes < L.total || (reinterpret_cast<uintptr_t>(fbp_ws) & 255u)) return PCT_ERR_WORKSPACE;
+    char *w = static_cast<char *>(fbp_ws);
+    const size_t xb = size_t(plan->nvox) * (dtype == PCT_F64 ? 8 : 4);
+    if (!disjoint(x, xb, w, L.total)) return PCT_ERR_INVALID_ARG;
+    double *proj = reinterpret_cast<double *>(w + L.proj);
+    double *q = reinterpret_cast<double *>(w + L.q);
+    st = hip_status(launch_fbp_sinogram(f, protons_dev(p), p->n, b, reinterpret_cast<unsigned long long *>(w + L.sum),
+                                        reinterpret_cast<unsigned *>(w + L.cnt), proj, nullptr, stream));
+    if (st) return st;
+    st = hip_status(launch_fbp_filter(f, proj, q, stream));
+    if (st) return st;
+    return hip_status(launch_fbp_backproject(f, grid_dev(plan->grid), q, x, dtype, stream));
 }
 
 const char *pct_status_string(int status)

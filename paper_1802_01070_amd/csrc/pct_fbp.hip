@@ -1,0 +1,193 @@
+// Filtered back-projection (FBP) image, the initial iterate of the iterative
+// solve (Section I).  Textbook parallel-beam FBP slice by slice along each
+// proton's straight entry-to-exit chord (Kak & Slaney, Principles of
+// Computerized Tomographic Imaging, ch. 3):
+//
+//   k_fbp_bin          one thread per proton: angle, lateral and slice bin of
+//                      the chord at depth u = 0; one 64-bit fixed-point atomic
+//                      for the WEPL sum and one 32-bit atomic for the count
+//                      (integer sums: the result does not depend on the order)
+//   k_fbp_mean         one thread per bin: projection = mean WEPL (0 if empty)
+//   k_fbp_filter       one workgroup per (slice, angle) row: Ram-Lak ramp
+//                      filter as a direct convolution over the row, staged in LDS
+//   k_fbp_backproject  one thread per voxel: sum over the angles of the
+//                      filtered row, linearly interpolated at the voxel's
+//                      lateral coordinate; the angles' sines and cosines in LDS;
+//                      workgroups of a slice stay on one XCD so that the slice's
+//                      filtered rows are read through one L2
+//
+// Sinograms are laid out [iz][angle][k] (a slice's rows are contiguous).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "pct_internal.h"
+
+namespace pct {
+
+constexpr double kFbpScale = 16777216.0;       // 2^24: WEPL fixed point of the bin sums
+constexpr double kFbpInvScale = 1.0 / 16777216.0;
+constexpr int kFbpWG = 256;
+
+__global__ void __launch_bounds__(kFbpWG) k_fbp_clear(unsigned long long *sum, unsigned *cnt, int64_t nb)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nb; i += int64_t(gridDim.x) * blockDim.x) {
+        sum[i] = 0ull;
+        cnt[i] = 0u;
+    }
+}
+
+__global__ void __launch_bounds__(kFbpWG) k_fbp_bin(ProtonsDev p, const float *__restrict__ b, int64_t n,
+                                                    FbpDev f, unsigned long long *sum, unsigned *cnt)
+{
+    // the bin decisions follow the definition's operation order exactly (no
+    // contraction into fused multiply-adds)
+#pragma clang fp contract(off)
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const double t_in = p.t_in[i], t_out = p.t_out[i], v_in = p.v_in[i], v_out = p.v_out[i];
+        const double phi = p.gantry[i], bi = b[i];
+        const double tc = t_in + f.w * (t_out - t_in);
+        const double vc = v_in + f.w * (v_out - v_in);
+        if (!(isfinite(tc) && isfinite(vc) && isfinite(phi) && isfinite(bi))) continue;
+        if (!(fabs(bi) < kFbpMaxWepl)) continue;
+        const double fk = floor((tc - f.t0) / f.dt);
+        const double fz = floor((vc - f.z0) / f.pz);
+        if (!(fk >= 0.0 && fk < double(f.n_t) && fz >= 0.0 && fz < double(f.nz))) continue;
+        double fa = fmod(floor(phi / f.dphi + 0.5), double(f.n_ang));
+        if (fa < 0.0) fa += double(f.n_ang);
+        const int64_t bin = (int64_t(fz) * f.n_ang + int64_t(fa)) * f.n_t + int64_t(fk);
+        atomicAdd(sum + bin, static_cast<unsigned long long>(llrint(bi * kFbpScale)));
+        atomicAdd(cnt + bin, 1u);
+    }
+}
+
+__global__ void __launch_bounds__(kFbpWG) k_fbp_mean(const unsigned long long *__restrict__ sum,
+                                                     const unsigned *__restrict__ cnt, int64_t nb, double *proj,
+                                                     int32_t *count)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nb; i += int64_t(gridDim.x) * blockDim.x) {
+        const unsigned c = cnt[i];
+        const double s = double(static_cast<long long>(sum[i])) * kFbpInvScale;
+        proj[i] = c ? s / double(c) : 0.0;
+        if (count) count[i] = int32_t(c);
+    }
+}
+
+// q_k = dt sum_n p_n h(k - n) with h(0) = 1/(4 dt^2), h(m) = -1/(pi^2 m^2 dt^2)
+// for odd m, 0 for even m: q_k = (p_k / 4 - sum_{odd m} p_{k-m} / (pi^2 m^2)) / dt.
+// LDS: the row (n_t doubles) and the odd-tap coefficients 1/(pi^2 m^2) (n_t).
+__global__ void __launch_bounds__(kFbpWG) k_fbp_filter(const double *__restrict__ proj, double *__restrict__ q,
+                                                       int n_t, double dt)
+{
+    extern __shared__ double lds[];
+    double *row = lds;
+    double *cm = lds + n_t;
+    const int64_t base = int64_t(blockIdx.x) * n_t;
+    for (int k = threadIdx.x; k < n_t; k += blockDim.x) {
+        row[k] = proj[base + k];
+        const double m = double(k);
+        cm[k] = (k & 1) ? 1.0 / (M_PI * M_PI * m * m) : 0.0;
+    }
+    __syncthreads();
+    const double inv_dt = 1.0 / dt;
+    for (int k = threadIdx.x; k < n_t; k += blockDim.x) {
+        double acc = 0.0;
+        // odd distances m = 1, 3, ... on both sides of k
+        for (int m = 1; m < n_t; m += 2) {
+            const double c = cm[m];
+            const double lo = k - m >= 0 ? row[k - m] : 0.0;
+            const double hi = k + m < n_t ? row[k + m] : 0.0;
+            acc += c * (lo + hi);
+        }
+        q[base + k] = (0.25 * row[k] - acc) * inv_dt;
+    }
+}
+
+// x(voxel) = (pi / n_ang) sum_a q_{iz,a}(t), t = -x sin(phi_a) + y cos(phi_a),
+// linear interpolation between bin centres t0 + (k + 1/2) dt, zero beyond the
+// outer bins.  Grid: 8 * ceil(nz / 8) * tiles workgroups; workgroup L runs on
+// XCD L % 8 and takes slice (L % 8) + 8 * ((L / 8) / tiles), tile (L / 8) % tiles.
+template <typename T>
+__global__ void __launch_bounds__(kFbpWG) k_fbp_backproject(const double *__restrict__ q, T *__restrict__ x,
+                                                            FbpDev f, GridDev g, int tiles)
+{
+    extern __shared__ double lds[];
+    double *cs = lds;            // cos(phi_a)
+    double *sn = lds + f.n_ang;  // sin(phi_a)
+    const int L = blockIdx.x;
+    const int xcd = L % 8, j = L / 8;
+    const int iz = xcd + 8 * (j / tiles);
+    const int tile = j % tiles;
+    if (iz >= g.n[2]) return;   // whole workgroup: no barrier below is skipped by part of it
+    for (int a = threadIdx.x; a < f.n_ang; a += blockDim.x) sincos(double(a) * f.dphi, &sn[a], &cs[a]);
+    __syncthreads();
+    const int64_t plane = int64_t(g.n[0]) * g.n[1];
+    const int64_t v = int64_t(tile) * blockDim.x + threadIdx.x;
+    if (v >= plane) return;
+    const int ix = int(v % g.n[0]), iy = int(v / g.n[0]);
+    const double xc = g.lo[0] + (ix + 0.5) * g.pitch[0];
+    const double yc = g.lo[1] + (iy + 0.5) * g.pitch[1];
+    const double inv_dt = 1.0 / f.dt;
+    const double *qs = q + int64_t(iz) * f.n_ang * f.n_t;
+    double acc = 0.0;
+    for (int a = 0; a < f.n_ang; ++a) {
+        const double t = -xc * sn[a] + yc * cs[a];
+        const double s = (t - f.t0) * inv_dt - 0.5;
+        const double fk = floor(s);
+        const double w = s - fk;
+        const double *row = qs + int64_t(a) * f.n_t;
+        double q0 = 0.0, q1 = 0.0;
+        if (fk >= 0.0 && fk < double(f.n_t)) q0 = row[int(fk)];
+        if (fk >= -1.0 && fk < double(f.n_t - 1)) q1 = row[int(fk) + 1];
+        acc += (1.0 - w) * q0 + w * q1;
+    }
+    x[int64_t(iz) * plane + v] = T(acc * (M_PI / f.n_ang));
+}
+
+static unsigned grid_stride_blocks(int64_t n)
+{
+    return unsigned(std::max<int64_t>(1, std::min<int64_t>(8192, (n + kFbpWG - 1) / kFbpWG)));
+}
+
+int launch_fbp_sinogram(const FbpDev &f, const ProtonsDev &p, int64_t n, const float *b, unsigned long long *sum,
+                        unsigned *cnt, double *proj, int32_t *count, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nb = int64_t(f.nz) * f.n_ang * f.n_t;
+    hipLaunchKernelGGL(k_fbp_clear, dim3(grid_stride_blocks(nb)), dim3(kFbpWG), 0, s, sum, cnt, nb);
+    if (n > 0)
+        hipLaunchKernelGGL(k_fbp_bin, dim3(grid_stride_blocks(n)), dim3(kFbpWG), 0, s, p, b, n, f, sum, cnt);
+    hipLaunchKernelGGL(k_fbp_mean, dim3(grid_stride_blocks(nb)), dim3(kFbpWG), 0, s, sum, cnt, nb, proj, count);
+    return hipGetLastError();
+}
+
+int launch_fbp_filter(const FbpDev &f, const double *proj, double *q, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned rows = unsigned(int64_t(f.nz) * f.n_ang);
+    hipLaunchKernelGGL(k_fbp_filter, dim3(rows), dim3(kFbpWG), size_t(2) * f.n_t * sizeof(double), s, proj, q,
+                       f.n_t, f.dt);
+    return hipGetLastError();
+}
+
+int launch_fbp_backproject(const FbpDev &f, const GridDev &g, const double *q, void *x, int32_t dtype,
+                           void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t plane = int64_t(g.n[0]) * g.n[1];
+    const int tiles = int((plane + kFbpWG - 1) / kFbpWG);
+    const unsigned grid = unsigned(8 * ((g.n[2] + 7) / 8) * int64_t(tiles));
+    const size_t lds = size_t(2) * f.n_ang * sizeof(double);
+    if (dtype == PCT_F64)
+        hipLaunchKernelGGL(k_fbp_backproject<double>, dim3(grid), dim3(kFbpWG), lds, s, q, static_cast<double *>(x),
+                           f, g, tiles);
+    else
+        hipLaunchKernelGGL(k_fbp_backproject<float>, dim3(grid), dim3(kFbpWG), lds, s, q, static_cast<float *>(x), f,
+                           g, tiles);
+    return hipGetLastError();
+}
+
+}  // namespace pct

@@ -73,6 +73,24 @@ enum : int { kHdrStatus = 0, kHdrRange0 = 2, kHdrRange1 = 4, kHdrSlots = 8 };
 
 Layout layout_for(int64_t nvox, int K, int dtype);
 
+// FBP binning and back-projection geometry, passed to kernels by value.
+struct FbpDev {
+    int32_t n_ang, n_t, nz;
+    double t0, dt, dphi;  // lateral bins [t0 + k dt, t0 + (k+1) dt); angle bin width 2 pi / n_ang
+    double w;             // chord parameter of depth u = 0: -u_in / (u_out - u_in)
+    double z0, pz;        // slice origin and thickness (mm)
+};
+constexpr double kFbpMaxWepl = 1048576.0;  // 2^20 mm: |b| at or beyond it is not a WEPL (dropped)
+constexpr int kFbpMaxAngles = 4096;        // sines and cosines of every angle bin in LDS
+constexpr int kFbpMaxLateral = 4096;       // a sinogram row and its filter taps in LDS
+
+// FBP workspace layout (byte offsets): bin sums (int64 fixed point), bin
+// counts (uint32), projections and filtered projections (double).
+struct FbpLayout {
+    size_t sum, cnt, proj, q, total;
+};
+FbpLayout fbp_layout(int64_t nbins);
+
 }  // namespace pct
 
 struct pct_plan {
@@ -123,6 +141,11 @@ int launch_region_select(const pct_plan &pl, const ProtonsDev &p, int64_t n, con
 int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,
               void *stream);
 int upload_table(const pct_plan &pl, void *ws, void *stream);
+int launch_fbp_sinogram(const FbpDev &f, const ProtonsDev &p, int64_t n, const float *b, unsigned long long *sum,
+                        unsigned *cnt, double *proj, int32_t *count, void *stream);
+int launch_fbp_filter(const FbpDev &f, const double *proj, double *q, void *stream);
+int launch_fbp_backproject(const FbpDev &f, const GridDev &g, const double *q, void *x, int32_t dtype,
+                           void *stream);
 int profile_read(pct_plan &pl, double ms[2], int64_t launches[2]);
 void profile_release(pct_plan &pl);
 void graph_release(pct_plan &pl);

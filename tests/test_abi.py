@@ -297,3 +297,51 @@ def test_library_has_no_oracle_dependency():
     # the product library must not link, load or name the oracle
     data = open(_lib.LIB_PATH, "rb").read()
     assert b"orc_" not in data and b"liborc" not in data
+
+
+def test_fbp_calls_validate(plan):
+    # plan: 8 x 8 x 2 grid.  Every call below fails validation on the host, so
+    # nothing is launched.
+    L = _lib.lib()
+    G = _lib.pct_fbp_geom
+    good = G(12, 16, -8.0, 1.0)
+    nb = 2 * 12 * 16
+    sz = C.c_size_t()
+    assert L.pct_fbp_workspace_size(plan, C.byref(good), C.byref(sz)) == 0
+    align = lambda v: (v + 255) // 256 * 256
+    assert sz.value == align(8 * nb) + align(4 * nb) + 2 * align(8 * nb)
+    for bad in (G(0, 16, -8.0, 1.0), G(4097, 16, -8.0, 1.0), G(12, 0, -8.0, 1.0), G(12, 4097, -8.0, 1.0),
+                G(12, 16, float("nan"), 1.0), G(12, 16, -8.0, 0.0), G(12, 16, -8.0, -1.0),
+                G(12, 16, -8.0, float("inf"))):
+        assert L.pct_fbp_workspace_size(plan, C.byref(bad), C.byref(sz)) == -1
+        assert L.pct_fbp_filter(plan, C.byref(bad), C.c_void_p(0x10000), C.c_void_p(0x20000), None) == -1
+    assert L.pct_fbp_workspace_size(plan, None, C.byref(sz)) == -1
+    assert L.pct_fbp_workspace_size(plan, C.byref(good), None) == -1
+    p = fake_protons(100)
+    b = C.c_void_p(0x8000)
+    x = C.c_void_p(0x40000000)
+    ws = C.c_void_p(0x7F0000000000)
+    wsb = align(8 * nb) + align(4 * nb) + 2 * align(8 * nb)
+    # workspace missing, too small, misaligned
+    assert L.pct_fbp(plan, C.byref(good), C.byref(p), b, x, 0, None, wsb, None) == -2
+    assert L.pct_fbp(plan, C.byref(good), C.byref(p), b, x, 0, ws, wsb - 1, None) == -2
+    assert L.pct_fbp(plan, C.byref(good), C.byref(p), b, x, 0, C.c_void_p(0x7F0000000010), wsb, None) == -2
+    # x inside the workspace, bad dtype, missing b or x
+    assert L.pct_fbp(plan, C.byref(good), C.byref(p), b, C.c_void_p(0x7F0000000100), 0, ws, wsb, None) == -1
+    assert L.pct_fbp(plan, C.byref(good), C.byref(p), b, x, 7, ws, wsb, None) == -1
+    assert L.pct_fbp(plan, C.byref(good), C.byref(p), None, x, 0, ws, wsb, None) == -1
+    assert L.pct_fbp(plan, C.byref(good), C.byref(p), b, None, 0, ws, wsb, None) == -1
+    # sinogram: output overlapping the sums, workspace without its sum and count parts
+    assert L.pct_fbp_sinogram(plan, C.byref(good), C.byref(p), b, ws, None, ws, wsb, None) == -1
+    assert L.pct_fbp_sinogram(plan, C.byref(good), C.byref(p), b, x, None, ws, align(8 * nb), None) == -2
+    assert L.pct_fbp_sinogram(plan, C.byref(good), C.byref(p), b, None, None, ws, wsb, None) == -1
+    # filter in place, back-projection onto its own input
+    assert L.pct_fbp_filter(plan, C.byref(good), x, C.c_void_p(0x40000000 + 8), None) == -1
+    assert L.pct_fbp_backproject(plan, C.byref(good), x, C.c_void_p(0x40000000 + 64), 0, None) == -1
+    assert L.pct_fbp_backproject(plan, C.byref(good), x, C.c_void_p(0x50000000), 2, None) == -1
+    # too many bins for a 32-bit bin index
+    big = G(4096, 4096, -8.0, 1.0)
+    st, h = plan_for(Grid(8, 8, 200), MLPModel(u_in=-5, u_out=5))
+    assert st == 0
+    assert L.pct_fbp_workspace_size(h, C.byref(big), C.byref(sz)) == -1
+    L.pct_plan_destroy(h)

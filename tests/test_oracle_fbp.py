@@ -79,6 +79,7 @@ def test_binning_by_hand():
             ((0.0, 1.5, 0, 0, 0.0, 0.9, 0, 0, 0.0), 1.0),                # v_c 1.2: above the grid, dropped
             ((0.0, 0.5, 0, 0, 0.0, 0.5, 0, 0, 0.0), np.nan),             # non-finite b: dropped
             ((0.0, 0.5, 0, 0, 0.0, 0.5, 0, 0, np.inf), 1.0),             # non-finite angle: dropped
+            ((0.0, 0.5, 0, 0, 0.0, 0.5, 0, 0, 0.0), 2.0 ** 20),          # not a WEPL: dropped
             ((-2.0, -1.0, 0, 0, -2.0, -1.0, 0, 0, -0.3), 4.0)]           # lower edges, angle -0.3 -> bin 0
     pr = synth.make_rays(grid, mlp, [r for r, _ in rays])
     b = np.array([v for _, v in rays], dtype=np.float32)
