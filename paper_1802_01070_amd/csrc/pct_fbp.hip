@@ -3,10 +3,13 @@
 // proton's straight entry-to-exit chord (Kak & Slaney, Principles of
 // Computerized Tomographic Imaging, ch. 3):
 //
-//   k_fbp_bin          one thread per proton: angle, lateral and slice bin of
-//                      the chord at depth u = 0; one 64-bit fixed-point atomic
-//                      for the WEPL sum and one 32-bit atomic for the count
-//                      (integer sums: the result does not depend on the order)
+//   k_fbp_bin_lds      one thread per proton: angle, lateral and slice bin of
+//                      the chord at depth u = 0; bins of the workgroup's home
+//                      angle summed in LDS, flushed once; k_fbp_bin, one
+//                      64-bit fixed-point atomic for the WEPL sum and one
+//                      32-bit atomic for the count per proton, when they do
+//                      not fit (integer sums: the result does not depend on the
+//                      order or on the kernel)
 //   k_fbp_mean         one thread per bin: projection = mean WEPL (0 if empty)
 //   k_fbp_filter       one workgroup per (slice, angle) row: Ram-Lak ramp
 //                      filter as a direct convolution over the row, staged in LDS
@@ -61,6 +64,73 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_bin(ProtonsDev p, const float *_
         const int64_t bin = (int64_t(fz) * f.n_ang + int64_t(fa)) * f.n_t + int64_t(fk);
         atomicAdd(sum + bin, static_cast<unsigned long long>(llrint(bi * kFbpScale)));
         atomicAdd(cnt + bin, 1u);
+    }
+}
+
+// Privatised binning for angle-sorted scans (the acquisition order of a
+// rotating gantry): workgroup w takes the contiguous protons [w chunk,
+// (w+1) chunk); the bins of its home angle (that of its middle proton) are
+// summed in LDS, one packed 64-bit word per (slice, lateral) bin -- count in
+// bits 63..48, the 2^-24 mm fixed-point sum as a signed value below (|sum| <
+// 2^47 and count < 2^15 for chunks of at most 8192 protons with |b| < 2^10
+// mm) -- and flushed with one pair of global atomics per non-empty bin; other
+// protons go straight to the global bins.  Integer sums: the result is that
+// of k_fbp_bin bit for bit.
+constexpr double kFbpLdsWepl = 1024.0;
+constexpr int64_t kFbpMaxChunk = 8192;
+
+__global__ void __launch_bounds__(kFbpWG) k_fbp_bin_lds(ProtonsDev p, const float *__restrict__ b, int64_t n,
+                                                        int64_t chunk, FbpDev f, unsigned long long *sum,
+                                                        unsigned *cnt)
+{
+#pragma clang fp contract(off)
+    extern __shared__ unsigned long long hist[];
+    const int nzt = f.nz * f.n_t;
+    const int64_t lo = int64_t(blockIdx.x) * chunk;
+    const int64_t hi = min(n, lo + chunk);
+    int home = -1;
+    {
+        const double phi = p.gantry[lo + (hi - 1 - lo) / 2];
+        if (isfinite(phi)) {
+            double fa = fmod(floor(phi / f.dphi + 0.5), double(f.n_ang));
+            if (fa < 0.0) fa += double(f.n_ang);
+            home = int(fa);
+        }
+    }
+    for (int i = threadIdx.x; i < nzt; i += blockDim.x) hist[i] = 0ull;
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double t_in = p.t_in[i], t_out = p.t_out[i], v_in = p.v_in[i], v_out = p.v_out[i];
+        const double phi = p.gantry[i], bi = b[i];
+        const double tc = t_in + f.w * (t_out - t_in);
+        const double vc = v_in + f.w * (v_out - v_in);
+        if (!(isfinite(tc) && isfinite(vc) && isfinite(phi) && isfinite(bi))) continue;
+        if (!(fabs(bi) < kFbpMaxWepl)) continue;
+        const double fk = floor((tc - f.t0) / f.dt);
+        const double fz = floor((vc - f.z0) / f.pz);
+        if (!(fk >= 0.0 && fk < double(f.n_t) && fz >= 0.0 && fz < double(f.nz))) continue;
+        double fa = fmod(floor(phi / f.dphi + 0.5), double(f.n_ang));
+        if (fa < 0.0) fa += double(f.n_ang);
+        const long long qv = llrint(bi * kFbpScale);
+        if (int(fa) == home && fabs(bi) < kFbpLdsWepl) {
+            atomicAdd(hist + int(fz) * f.n_t + int(fk), (1ull << 48) + static_cast<unsigned long long>(qv));
+        } else {
+            const int64_t bin = (int64_t(fz) * f.n_ang + int64_t(fa)) * f.n_t + int64_t(fk);
+            atomicAdd(sum + bin, static_cast<unsigned long long>(qv));
+            atomicAdd(cnt + bin, 1u);
+        }
+    }
+    __syncthreads();
+    if (home < 0) return;
+    for (int i = threadIdx.x; i < nzt; i += blockDim.x) {
+        const unsigned long long wv = hist[i];
+        if (!wv) continue;
+        const long long sv = static_cast<long long>(wv << 16) >> 16;
+        const unsigned c = unsigned((wv - static_cast<unsigned long long>(sv)) >> 48);
+        const int iz = i / f.n_t, k = i - iz * f.n_t;
+        const int64_t bin = (int64_t(iz) * f.n_ang + home) * f.n_t + k;
+        atomicAdd(sum + bin, static_cast<unsigned long long>(sv));
+        atomicAdd(cnt + bin, c);
     }
 }
 
@@ -158,8 +228,26 @@ int launch_fbp_sinogram(const FbpDev &f, const ProtonsDev &p, int64_t n, const f
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t nb = int64_t(f.nz) * f.n_ang * f.n_t;
     hipLaunchKernelGGL(k_fbp_clear, dim3(grid_stride_blocks(nb)), dim3(kFbpWG), 0, s, sum, cnt, nb);
-    if (n > 0)
-        hipLaunchKernelGGL(k_fbp_bin, dim3(grid_stride_blocks(n)), dim3(kFbpWG), 0, s, p, b, n, f, sum, cnt);
+    if (n > 0) {
+        // privatised bins when one angle's (slice, lateral) bins fit the
+        // workgroup's LDS on this device, else straight global atomics
+        const size_t lds = size_t(f.nz) * f.n_t * sizeof(unsigned long long);
+        int dev = 0, max_lds = 0;
+        bool priv = hipGetDevice(&dev) == hipSuccess &&
+                    hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+                    lds <= size_t(max_lds);
+        if (priv && lds > 65536)
+            priv = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fbp_bin_lds),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) == hipSuccess;
+        (void)hipGetLastError();
+        if (priv) {
+            const int64_t chunk = std::min<int64_t>(kFbpMaxChunk, std::max<int64_t>(1024, (n + 1023) / 1024));
+            hipLaunchKernelGGL(k_fbp_bin_lds, dim3(unsigned((n + chunk - 1) / chunk)), dim3(kFbpWG), lds, s, p, b, n,
+                               chunk, f, sum, cnt);
+        } else {
+            hipLaunchKernelGGL(k_fbp_bin, dim3(grid_stride_blocks(n)), dim3(kFbpWG), 0, s, p, b, n, f, sum, cnt);
+        }
+    }
     hipLaunchKernelGGL(k_fbp_mean, dim3(grid_stride_blocks(nb)), dim3(kFbpWG), 0, s, sum, cnt, nb, proj, count);
     return hipGetLastError();
 }

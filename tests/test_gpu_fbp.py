@@ -43,16 +43,24 @@ def image_tol(geo, ref):
     return np.pi / (2.0 * geo.dt) * 2.0 ** -25 + 1e-11 * max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("cfg,m,n_ang", [(1, 200000, 90), (2, 2000000, 180), ("cont", 1000000, 180),
-                                         (1, 50000, 7)])
-def test_sinogram_matches_oracle(cfg, m, n_ang):
+# (cfg, protons, angle bins, shuffled): angle-sorted scans take the LDS-privatised
+# binning where one angle's bins fit in LDS (the 256 x 256 x 64 grid's do not);
+# a shuffled scan sends almost every proton to the global bins
+@pytest.mark.parametrize("cfg,m,n_ang,shuffle", [(1, 200000, 90, False), (2, 2000000, 180, False),
+                                                 ("cont", 1000000, 180, False), (1, 50000, 7, False),
+                                                 (3, 1000000, 360, False), (2, 1000000, 180, True)])
+def test_sinogram_matches_oracle(cfg, m, n_ang, shuffle):
     sc = scan(cfg, m)
     g = geom_of(sc, n_ang)
-    say(f"fbp sinogram cfg{cfg} m={sc.m} geom={g}")
+    say(f"fbp sinogram cfg{cfg} m={sc.m} geom={g} shuffled={shuffle}")
+    prot, bb = sc.protons, sc.b
+    if shuffle:
+        perm = np.random.default_rng(4).permutation(sc.m)
+        prot, bb = {k: v[perm] for k, v in prot.items()}, bb[perm]
     plan = api.Plan(sc.grid, sc.mlp, DEV)
-    pr = api.Protons(sc.protons, DEV)
-    proj, cnt = api.pct_fbp_sinogram(plan, pr, torch.from_numpy(sc.b).to(DEV), g)
-    rp, rc = ofbp.sinogram(sc.grid, sc.mlp, sc.protons, sc.b, g.n_angles, g.n_t, g.t0, g.dt)
+    pr = api.Protons(prot, DEV)
+    proj, cnt = api.pct_fbp_sinogram(plan, pr, torch.from_numpy(bb).to(DEV), g)
+    rp, rc = ofbp.sinogram(sc.grid, sc.mlp, prot, bb, g.n_angles, g.n_t, g.t0, g.dt)
     assert np.array_equal(cnt.cpu().numpy(), rc)
     assert int(rc.sum()) > 0.9 * sc.m
     # 2^-24 mm fixed point of each b against the FP64 sum
