@@ -309,7 +309,7 @@ int pct_region_layout(int32_t nz, int32_t n_regions, int32_t halo, int32_t *z_lo
                       int32_t *core_hi);
 
 /* Host only.  A plan for slices z_lo..z_hi of the parent's grid (same x-y
- * extent and MLP model, z origin moved up by z_lo slices). */
+ * extent, MLP model and hull setting, z origin moved up by z_lo slices). */
 int pct_plan_region(const pct_plan *parent, int32_t z_lo, int32_t z_hi, pct_plan **out);
 
 /* Step 2 of Algorithm 1 for one region: the records (and b) of the protons

@@ -50,6 +50,7 @@ class Plan:
         self.mlp = mlp
         self.device = torch.device(device)
         self.nvox = int(grid.nx) * int(grid.ny) * int(grid.nz)
+        self.hull = None
         h = _handle
         if h is None:
             h = C.c_void_p()
@@ -83,7 +84,9 @@ class Plan:
         o = self.grid.origin
         g = dataclasses.replace(self.grid, nz=int(z_hi) - int(z_lo) + 1,
                                 origin=(o[0], o[1], o[2] + int(z_lo) * self.grid.pitch[2]))
-        return Plan(g, self.mlp, self.device, _handle=h)
+        sub = Plan(g, self.mlp, self.device, _handle=h)
+        sub.hull = getattr(self, "hull", None)        # the library copies the parent's hull setting
+        return sub
 
     def table(self):
         import numpy as np

@@ -556,7 +556,13 @@ int pct_plan_region(const pct_plan *parent, int32_t z_lo, int32_t z_hi, pct_plan
     pct_grid g = parent->grid;
     g.nz = z_hi - z_lo + 1;
     g.origin[2] = parent->grid.origin[2] + double(z_lo) * parent->grid.pitch[2];
-    return pct_plan_create(&g, &parent->mlp, out);
+    int st = pct_plan_create(&g, &parent->mlp, out);
+    if (st) return st;
+    (*out)->hull = parent->hull;
+    (*out)->hull_c[0] = parent->hull_c[0];
+    (*out)->hull_c[1] = parent->hull_c[1];
+    (*out)->hull_r = parent->hull_r;
+    return PCT_OK;
 }
 
 int pct_region_select(const pct_plan *plan, const pct_protons *p, const float *b, int32_t z_lo, int32_t z_hi,

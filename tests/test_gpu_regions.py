@@ -28,6 +28,13 @@ def _setup():
     torch.cuda.synchronize()
 
 
+@pytest.fixture(autouse=True)
+def _hull_off():
+    oracle.set_hull(None)
+    yield
+    oracle.set_hull(None)
+
+
 _scans = {}
 
 
@@ -143,18 +150,23 @@ def test_select_slices_round_trip():
         assert torch.all(y[:9 * plane] == -1) and torch.all(y[11 * plane:] == -1)
 
 
-@pytest.mark.parametrize("n_reg,halo,dtype,tol", [(2, 3, torch.float64, 1e-10), (3, 2, torch.float64, 1e-10),
-                                                  (2, 3, torch.float32, 1e-5)])
-def test_region_drop_matches_region_oracle(n_reg, halo, dtype, tol):
+@pytest.mark.parametrize("n_reg,halo,dtype,tol,hull", [(2, 3, torch.float64, 1e-10, None),
+                                                       (3, 2, torch.float64, 1e-10, None),
+                                                       (2, 3, torch.float32, 1e-5, None),
+                                                       (2, 3, torch.float64, 1e-10, 29.0)])
+def test_region_drop_matches_region_oracle(n_reg, halo, dtype, tol, hull):
     sc = scan("regions")
     c = sc.cfg
-    say(f"region DROP R={n_reg} halo={halo} {dtype} m={sc.m}")
+    say(f"region DROP R={n_reg} halo={halo} {dtype} m={sc.m} hull={hull}")
     plan = api.Plan(sc.grid, sc.mlp, DEV)
+    if hull is not None:
+        plan.set_hull(hull)                 # region plans inherit it
+    oracle.set_hull(hull)
     pr = api.Protons(sc.protons, DEV)
     b = torch.from_numpy(sc.b).to(DEV)
     x0 = np.random.default_rng(4).uniform(0.8, 1.2, sc.grid.nvox)
     x = torch.from_numpy(x0).to(DEV, dtype)
-    x0_used = x.double().cpu().numpy()
+    x0_used = x0.astype(np.float32 if dtype == torch.float32 else np.float64).astype(np.float64)
     # one sweep, then one more on the same per-region state
     state = api.region_drop(plan, pr, b, x, n_reg, halo, c.block, c.lam, 1)
     api.region_drop(plan, pr, b, x, n_reg, halo, c.block, c.lam, 1, regions=state)
@@ -166,3 +178,4 @@ def test_region_drop_matches_region_oracle(n_reg, halo, dtype, tol):
     assert err.max() <= tol
     for s in state:
         assert api.pct_device_status(s["plan"]) == 0
+        assert s["plan"].hull == plan.hull
