@@ -133,10 +133,10 @@ struct DotSink {
 };
 
 template <typename T, bool HULL>
-__global__ void __launch_bounds__(kWG) k_forward(ProtonsDev p, int64_t n, const T *__restrict__ x, T *y, T *nrm2,
-                                                 const PathSrc src,  GridDev g, unsigned *status)
+__global__ void __launch_bounds__(kWG) k_forward(ProtonsDev p, int64_t first, int64_t n, const T *__restrict__ x,
+                                                 T *y, T *nrm2, const PathSrc src, GridDev g, unsigned *status)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t i = first + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     Rec r = load_rec(p, i);
     DotSink<T> s;
@@ -168,11 +168,11 @@ struct ScatterSink {
 };
 
 template <typename T, bool HULL>
-__global__ void __launch_bounds__(kWG) k_backproject(ProtonsDev p, int64_t n, const T *__restrict__ rv, T *gout,
-                                                     const PathSrc src,  GridDev g,
+__global__ void __launch_bounds__(kWG) k_backproject(ProtonsDev p, int64_t first, int64_t n,
+                                                     const T *__restrict__ rv, T *gout, const PathSrc src, GridDev g,
                                                      unsigned *status)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t i = first + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double ri = double(rv[i]);
     if (ri == 0.0) return;
@@ -1599,6 +1599,15 @@ int launch_trace(const pct_plan &pl, const ProtonsDev &p, int64_t first, int64_t
     return hipGetLastError();
 }
 
+// Launches of the one-lane-per-proton kernels, in pieces of at most 2^30
+// workgroups (protons [first, first + count) per piece).
+template <class F>
+static void launch_pieces(int64_t n, F &&piece)
+{
+    const int64_t max_n = int64_t(kWG) << 30;
+    for (int64_t first = 0; first < n; first += max_n) piece(first, std::min<int64_t>(n - first, max_n));
+}
+
 int launch_forward(const pct_plan &pl, const ProtonsDev &p, int64_t n, const void *x, int dtype, void *y,
                    void *nrm2, void *ws, void *stream)
 {
@@ -1609,14 +1618,16 @@ int launch_forward(const pct_plan &pl, const ProtonsDev &p, int64_t n, const voi
     GridDev g = grid_dev(pl.grid);
     auto go = [&](auto hull) {
         constexpr bool H = decltype(hull)::value;
-        if (dtype == PCT_F64)
-            hipLaunchKernelGGL((k_forward<double, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
-                               static_cast<const double *>(x), static_cast<double *>(y),
-                               static_cast<double *>(nrm2), src, g, status);
-        else
-            hipLaunchKernelGGL((k_forward<float, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
-                               static_cast<const float *>(x), static_cast<float *>(y), static_cast<float *>(nrm2),
-                               src, g, status);
+        launch_pieces(n, [&](int64_t first, int64_t cnt) {
+            if (dtype == PCT_F64)
+                hipLaunchKernelGGL((k_forward<double, H>), dim3(grid_for(cnt)), dim3(kWG), 0, s, p, first,
+                                   first + cnt, static_cast<const double *>(x), static_cast<double *>(y),
+                                   static_cast<double *>(nrm2), src, g, status);
+            else
+                hipLaunchKernelGGL((k_forward<float, H>), dim3(grid_for(cnt)), dim3(kWG), 0, s, p, first,
+                                   first + cnt, static_cast<const float *>(x), static_cast<float *>(y),
+                                   static_cast<float *>(nrm2), src, g, status);
+        });
     };
     if (src.hull)
         go(std::true_type{});
@@ -1635,12 +1646,16 @@ int launch_backproject(const pct_plan &pl, const ProtonsDev &p, int64_t n, const
     GridDev g = grid_dev(pl.grid);
     auto go = [&](auto hull) {
         constexpr bool H = decltype(hull)::value;
-        if (dtype == PCT_F64)
-            hipLaunchKernelGGL((k_backproject<double, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
-                               static_cast<const double *>(r), static_cast<double *>(gout), src, g, status);
-        else
-            hipLaunchKernelGGL((k_backproject<float, H>), dim3(grid_for(n)), dim3(kWG), 0, s, p, n,
-                               static_cast<const float *>(r), static_cast<float *>(gout), src, g, status);
+        launch_pieces(n, [&](int64_t first, int64_t cnt) {
+            if (dtype == PCT_F64)
+                hipLaunchKernelGGL((k_backproject<double, H>), dim3(grid_for(cnt)), dim3(kWG), 0, s, p, first,
+                                   first + cnt, static_cast<const double *>(r), static_cast<double *>(gout), src,
+                                   g, status);
+            else
+                hipLaunchKernelGGL((k_backproject<float, H>), dim3(grid_for(cnt)), dim3(kWG), 0, s, p, first,
+                                   first + cnt, static_cast<const float *>(r), static_cast<float *>(gout), src, g,
+                                   status);
+        });
     };
     if (src.hull)
         go(std::true_type{});

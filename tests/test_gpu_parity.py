@@ -199,6 +199,34 @@ def test_backproject(cfg, m, dtype):
     assert_status_clean(plan)
 
 
+def test_projections_with_long_paths():
+    # 3000 MLP segments per path (step 0.02 mm); the walk of each segment
+    # covers a fraction of a voxel
+    grid = Grid(64, 64, 4)
+    mlp = MLPModel(u_in=-30.0, u_out=30.0, step=0.02)
+    rng = np.random.default_rng(6)
+    n = 3000
+    t = rng.uniform(-25, 25, n)
+    th = rng.normal(0, 0.01, n)
+    v = rng.uniform(-1.5, 1.5, n)
+    rays = np.stack([t, v, th, th * 0.1, t + 60 * th + rng.normal(0, 0.3, n), v, th, th * 0.1,
+                     rng.uniform(0, 2 * np.pi, n)], axis=1)
+    pr_np = synth.make_rays(grid, mlp, rays)
+    plan = api.Plan(grid, mlp, DEV)
+    assert plan.K >= 3000
+    pr = api.Protons(pr_np, DEV)
+    x_np = np.random.default_rng(7).uniform(0.5, 1.5, grid.nvox)
+    y, n2 = api.pct_forward(plan, pr, torch.from_numpy(x_np).to(DEV), with_norm=True)
+    ry, rn2, _ = oracle.forward(grid, mlp, pr_np, x_np)
+    np.testing.assert_allclose(y.cpu().numpy(), ry, rtol=1e-12, atol=1e-11)
+    np.testing.assert_allclose(n2.cpu().numpy(), rn2, rtol=1e-12, atol=1e-11)
+    r_np = rng.standard_normal(n)
+    g = api.pct_backproject(plan, pr, torch.from_numpy(r_np).to(DEV))
+    ref = oracle.backproject(grid, mlp, pr_np, r_np)
+    assert np.abs(g.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert_status_clean(plan)
+
+
 def test_adjoint_on_gpu():
     sc = scan(2, 20000)
     plan, pr = gpu_setup(sc)
