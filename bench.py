@@ -79,6 +79,23 @@ def measured_traffic(workload: str, kernel: str):
     return float(t["hbm_bytes_per_launch"]), p
 
 
+def measured_fbp_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of an FBP kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the sources changed since."""
+    p = os.path.join(ROOT, "profiles", "traffic_fbp_cfg2.json")
+    if not os.path.exists(p):
+        return None, "no counter summary"
+    t = json.load(open(p))
+    if t.get("workload") != workload:
+        return None, "counters taken on another workload"
+    if t.get("sources_sha256") != kernel_sources_digest():
+        return None, "kernel sources changed since the counters were taken"
+    k = t.get("kernels", {}).get(kernel)
+    if k is None:
+        return None, f"no counters for {kernel}"
+    return float(k["hbm_bytes_per_launch"]), p
+
+
 def count_nonzeros(api, plan, pr, chunk=1 << 20):
     """Sum over protons of the path's merged (voxel, chord) pieces, from the
     trace kernel (max_nnz = 1: only the lengths are kept)."""
@@ -450,9 +467,10 @@ def run_fbp(args):
     ms = time_events(lambda: api.pct_fbp(plan, pr, b, geom, x=x, ws=ws), reps=steps) / 1.0
     # the three steps on their own (HIP events on the stream they run on)
     box = {}
-    t_sino = time_events(lambda: box.__setitem__("s", api.pct_fbp_sinogram(plan, pr, b, geom, ws=ws)), reps=3)
-    t_filt = time_events(lambda: box.__setitem__("q", api.pct_fbp_filter(plan, box["s"][0], geom)), reps=3)
-    t_bp = time_events(lambda: box.__setitem__("x", api.pct_fbp_backproject(plan, box["q"], geom)), reps=3)
+    # 20 repetitions each: the device work (0.1-0.3 ms per call) outlasts the host's enqueue
+    t_sino = time_events(lambda: box.__setitem__("s", api.pct_fbp_sinogram(plan, pr, b, geom, ws=ws)), reps=20)
+    t_filt = time_events(lambda: box.__setitem__("q", api.pct_fbp_filter(plan, box["s"][0], geom)), reps=20)
+    t_bp = time_events(lambda: box.__setitem__("x", api.pct_fbp_backproject(plan, box["q"], geom)), reps=20)
     nb = sc.grid.nz * geom.n_angles * geom.n_t
     log(f"[bench] FBP image {ms:.3f} ms (sinogram {t_sino:.3f}, filter {t_filt:.3f}, back-projection {t_bp:.3f})")
     bp_flops = float(sc.grid.nvox) * geom.n_angles * FBP_FLOPS_PER_VOXEL_ANGLE
@@ -467,11 +485,14 @@ def run_fbp(args):
                 "kernel": "k_fbp_clear + k_fbp_bin + k_fbp_mean", "kernel_avg_us": 1e3 * t_sino,
                 "algorithmic_bytes_per_launch": bin_bytes}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    kname = "k_fbp_backproject" if roof["bound"] == "alu" else "k_fbp_bin_lds"
+    traffic, source = measured_fbp_traffic(cfg.name, kname)
+    roof["traffic"] = traffic
+    roof["traffic_source"] = source
     # DROP from x0 = 1 and from the FBP image
-    n_sweeps = 6
+    n_sweeps = 0 if args.no_drop_compare else 6
     runs = {}
-    for name in ("x0_one", "x0_fbp"):
+    for name in (("x0_one", "x0_fbp") if n_sweeps else ()):
         xs = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
         api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1)      # warm-up (graph)
         if name == "x0_one":
@@ -511,6 +532,7 @@ def run_fbp(args):
         "cpu_baseline": cpu,
         "drop_from_x0": runs,
     }
+    calibration_copy(args, dev)
     print(json.dumps(out), flush=True)
 
 
@@ -527,6 +549,8 @@ def main():
                     help="radius (mm) of a z-cylinder object hull: per-proton paths between the hull crossings")
     ap.add_argument("--cpu-blocks", type=int, default=320)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per proton in the block kernel (0: automatic)")
+    ap.add_argument("--no-drop-compare", action="store_true",
+                    help="--config fbp: skip the DROP sweeps from x0 = 1 and from the FBP image")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -697,16 +721,24 @@ def main():
         cb, emax, emean = cpu_baseline(sc, cfg, xs.double().cpu().numpy(), nb, args.hull)
         out["cpu_baseline"] = cb
         out["rsp_err_vs_fp64_oracle"] = {"sample": f"first {nb} blocks of one sweep", "max": emax, "mean": emean}
-    if args.calib_copy_mib:
-        nbytes = args.calib_copy_mib << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB x3 done")
+    calibration_copy(args, dev)
     print(json.dumps(out), flush=True)
+
+
+def calibration_copy(args, dev):
+    """A plain device copy of known size, three times: the scale of the HBM
+    counters (FETCH_SIZE, WRITE_SIZE) is read off it."""
+    if not args.calib_copy_mib:
+        return
+    import torch
+    nbytes = args.calib_copy_mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {args.calib_copy_mib} MiB x3 done")
 
 
 if __name__ == "__main__":
