@@ -182,3 +182,21 @@ def test_drop_from_the_fbp_image_matches_oracle():
     err = np.abs(x.cpu().numpy() - ref).max()
     say(f"  FBP then DROP: {err:.3e}")
     assert err <= 2.0 * image_tol(g, ref) + 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_fbp_ignores_the_hull_and_follows_region_grids():
+    # straight chords: a hull setting does not change the image; a region plan
+    # bins v by its own slices (z origin moved up by z_lo slices)
+    sc = scan(2, 400000)
+    g = geom_of(sc, 180)
+    pr = api.Protons(sc.protons, DEV)
+    b = torch.from_numpy(sc.b).to(DEV)
+    plain = api.Plan(sc.grid, sc.mlp, DEV)
+    hull = api.Plan(sc.grid, sc.mlp, DEV).set_hull(92.0)
+    x0 = api.pct_fbp(plain, pr, b, g, dtype=torch.float64)
+    x1 = api.pct_fbp(hull, pr, b, g, dtype=torch.float64)
+    assert torch.equal(x0, x1)
+    reg = plain.region(10, 21)
+    xr = api.pct_fbp(reg, pr, b, g, dtype=torch.float64).cpu().numpy()
+    rx = ofbp.fbp(reg.grid, sc.mlp, sc.protons, sc.b, g.n_angles, g.n_t, g.t0, g.dt)
+    assert np.abs(xr - rx).max() <= image_tol(g, rx)
