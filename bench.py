@@ -51,16 +51,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_sources_digest() -> str:
-    """sha256 over the HIP sources of the library (the traffic counters below
-    are valid only for the kernels they were taken on)."""
+# Sources each profiled kernel is built from: its counters stay valid while
+# these files are unchanged.
+KERNEL_SOURCES = {
+    "k_drop_pipe": ("pct_internal.h", "pct_path.hpp", "pct_kernels.hip"),
+    "fbp": ("pct_internal.h", "pct_fbp.hip"),
+}
+
+
+def kernel_sources_digest(kernel: str = "k_drop_pipe") -> str:
+    """sha256 over the HIP sources a profiled kernel is built from (the
+    traffic counters are valid only for the kernels they were taken on)."""
     import hashlib
     d = os.path.join(ROOT, "paper_1802_01070_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".h", ".cpp")):
-            h.update(name.encode())
-            h.update(open(os.path.join(d, name), "rb").read())
+    for name in KERNEL_SOURCES[kernel]:
+        h.update(name.encode())
+        h.update(open(os.path.join(d, name), "rb").read())
     return h.hexdigest()
 
 
@@ -88,7 +95,7 @@ def measured_fbp_traffic(workload: str, kernel: str):
     t = json.load(open(p))
     if t.get("workload") != workload:
         return None, "counters taken on another workload"
-    if t.get("sources_sha256") != kernel_sources_digest():
+    if t.get("sources_sha256") != kernel_sources_digest("fbp"):
         return None, "kernel sources changed since the counters were taken"
     k = t.get("kernels", {}).get(kernel)
     if k is None:
