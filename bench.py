@@ -657,12 +657,12 @@ def main():
 
     ceiling = parallel_sweep_ceiling(api, plan, pr, x)
     # which block schedule pct_drop_iterate takes (the library's rules): FP32
-    # with 64 lanes per proton and a workspace sized for the block (the Plan
-    # default covers blocks up to 8192) traces ahead; other FP32 runs fuse the
-    # commit; FP64 runs the block kernel and a separate commit
+    # with 64 lanes per proton, blocks of at most 4096 protons and a workspace
+    # sized for the block traces ahead; other FP32 runs fuse the commit; FP64
+    # runs the block kernel and a separate commit
     lanes = args.lanes or (64 if max(sc.grid.nx, sc.grid.ny) >= 160 else 32 if max(sc.grid.nx, sc.grid.ny) >= 64
                            else 16)
-    if vdtype == torch.float32 and lanes == 64 and cfg.block <= 8192:
+    if vdtype == torch.float32 and lanes == 64 and cfg.block <= 4096:
         kname, kdesc = "k_drop_pipe", ("k_drop_pipe (trace of block t+1 into a row slot, DROP step of block t: "
                                        "a.x + |a|^2 + rho + D-weighted scatter, commit of block t-1)")
     elif vdtype == torch.float32:

@@ -189,11 +189,13 @@ typedef struct {
  * schedule).  This flag asks for the separate schedule: one block kernel and
  * one commit kernel per block. */
 #define PCT_DROP_SEPARATE_COMMIT 0x8u
-/* FP32 value type, 64 lanes per proton, workspace sized for the block (see
- * pct_workspace_size): by default the rows of block t+1 are traced in the
- * launch that runs the DROP step of block t (the rows do not depend on x), so
- * each block step no longer waits for its own walk; results are bitwise those
- * of the other schedules.  This flag asks for the plain fused schedule. */
+/* FP32 value type, 64 lanes per proton, blocks of at most 4096 protons,
+ * workspace sized for the block (see pct_workspace_size): by default the rows
+ * of block t+1 are traced in the launch that runs the DROP step of block t
+ * (the rows do not depend on x), so each block step no longer waits for its
+ * own walk; results are bitwise those of the other schedules.  Larger blocks
+ * take the plain fused schedule (faster there).  This flag asks for the plain
+ * fused schedule. */
 #define PCT_DROP_NO_TRACE_AHEAD 0x10u
 
 /* Workspace bytes for this plan and x of type dtype.  n > 0 adds two row

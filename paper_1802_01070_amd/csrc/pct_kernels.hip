@@ -1777,6 +1777,8 @@ static void launch_fused(int lanes, hipStream_t s, const ProtonsDev &p, const fl
 
 // Lanes per proton: enough lanes that each walks a few slabs of the dominant
 // axis, within the LDS budget of the staged vertex coordinates.
+constexpr int64_t kPipeMaxBlock = 4096;
+
 static int choose_lanes(const pct_plan &pl, int requested)
 {
     constexpr size_t kLdsBudget = 64 * 1024;
@@ -1967,7 +1969,11 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         }
     };
     const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT);
-    const bool pipe = fused && lanes == 64 && !(o.flags & PCT_DROP_NO_TRACE_AHEAD) &&
+    // tracing ahead doubles the workgroups of a launch; with blocks above
+    // kPipeMaxBlock protons the plain fused schedule is the faster one
+    // (measured: 3200-proton blocks 165 vs 169 ms per sweep traced ahead, 6400-proton
+    // blocks 953 vs 871 ms on the 256 x 256 x 64 scan)
+    const bool pipe = fused && lanes == 64 && !(o.flags & PCT_DROP_NO_TRACE_AHEAD) && o.block <= kPipeMaxBlock &&
                       ws_bytes >= L.total + 2 * slot_bytes(o.block);
     auto sweep = [&](hipStream_t s, bool record_events) {
         if constexpr (sizeof(T) == 4) {
