@@ -75,7 +75,7 @@ def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of the block kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary of this workload, or None when the kernel
     sources changed since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cfg2.json")
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cyl200.json")
     if not os.path.exists(p):
         return None, "no counter summary"
     t = json.load(open(p))
@@ -89,7 +89,7 @@ def measured_traffic(workload: str, kernel: str):
 def measured_fbp_traffic(workload: str, kernel: str):
     """HBM bytes per launch of an FBP kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None when the sources changed since."""
-    p = os.path.join(ROOT, "profiles", "traffic_fbp_cfg2.json")
+    p = os.path.join(ROOT, "profiles", "traffic_fbp_cyl200.json")
     if not os.path.exists(p):
         return None, "no counter summary"
     t = json.load(open(p))
@@ -179,7 +179,7 @@ def run_precision(args):
     """Precision form on the 2*10^7-proton 200x200x32 scan."""
     import torch
     from paper_1802_01070_amd import api, synth
-    cfg = synth.CONFIGS[4]
+    cfg = synth.WORKLOADS[4]
     m = args.protons or cfg.m
     log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
@@ -260,7 +260,7 @@ def run_gradient(args):
     """Differentiation form on the 2*10^7-proton 256x256x64 scan."""
     import torch
     from paper_1802_01070_amd import api, synth
-    cfg = synth.CONFIGS[5]
+    cfg = synth.WORKLOADS[5]
     m = args.protons or cfg.m
     log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
@@ -335,7 +335,7 @@ def run_block_sizes(args):
     """Block-size variants of the plain method on the 10^7-proton scan."""
     import torch
     from paper_1802_01070_amd import api, synth
-    cfg = synth.CONFIGS[2]
+    cfg = synth.WORKLOADS[2]
     m = args.protons or cfg.m
     log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
@@ -379,7 +379,7 @@ def run_regions(args):
     solve, sweep by sweep."""
     import torch
     from paper_1802_01070_amd import api, synth
-    cfg = synth.CONFIGS[2]
+    cfg = synth.WORKLOADS[2]
     m = args.protons or cfg.m
     n_sweeps = args.steps if args.steps != 12 else 6
     log(f"[bench] generating {cfg.name}: {m} protons")
@@ -455,7 +455,7 @@ def run_fbp(args):
     sweeps started from it against x0 = 1."""
     import torch
     from paper_1802_01070_amd import api, synth
-    cfg = synth.CONFIGS[2]
+    cfg = synth.WORKLOADS[2]
     m = args.protons or cfg.m
     log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
@@ -582,7 +582,7 @@ def main():
     if args.config == "fbp":
         return run_fbp(args)
     key = int(args.config) if args.config.isdigit() else args.config
-    cfg = synth.CONFIGS[key]
+    cfg = synth.WORKLOADS[key]
     m = args.protons or cfg.m
     log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()

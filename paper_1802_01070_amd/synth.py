@@ -14,7 +14,7 @@ no most-likely-path coefficients, no voxel walk, no DROP update.  It produces
 The paper's CTP404 datasets (Geant4-simulated and scanner data, Section IV-A)
 are not available; these scans stand in for them.  Their shape follows the
 paper's acquisition (discrete projection angles over a full rotation, Section
-IV-A) and the configurations listed in ``CONFIGS``.
+IV-A) and the configurations listed in ``WORKLOADS``.
 
 Physics stand-ins (not the reconstruction model):
 * exit deflections use the Fermi-Eyges covariance of a constant scattering
@@ -285,16 +285,16 @@ def _phantom(name: str, grid: Grid, seed: int) -> Phantom:
     raise KeyError(name)
 
 
-CONFIGS = {
-    1: ScanConfig("cfg1_cyl64_fp64", Grid(64, 64, 4), m=200_000, n_angles=90, r_hull=30.0, block=3200,
+WORKLOADS = {
+    1: ScanConfig("cyl64_fp64", Grid(64, 64, 4), m=200_000, n_angles=90, r_hull=30.0, block=3200,
                   lam=0.1, n_iter=6, phantom="cyl64", value_type="f64", seed=1001),
-    2: ScanConfig("cfg2_cyl200_fp32", Grid(200, 200, 32), m=10_000_000, n_angles=180, r_hull=100.0,
+    2: ScanConfig("cyl200_fp32", Grid(200, 200, 32), m=10_000_000, n_angles=180, r_hull=100.0,
                   block=3200, lam=0.1, n_iter=12, phantom="cyl200", seed=1002),
-    3: ScanConfig("cfg3_head256_sorted", Grid(256, 256, 64), m=50_000_000, n_angles=360, r_hull=110.0,
+    3: ScanConfig("head256_sorted", Grid(256, 256, 64), m=50_000_000, n_angles=360, r_hull=110.0,
                   block=6400, lam=0.1, n_iter=8, phantom="head256", order="angle_slab", seed=1003),
-    4: ScanConfig("cfg4_cyl200_lowprec", Grid(200, 200, 32), m=20_000_000, n_angles=180, r_hull=100.0,
+    4: ScanConfig("cyl200_lowprec", Grid(200, 200, 32), m=20_000_000, n_angles=180, r_hull=100.0,
                   block=3200, lam=0.1, n_iter=8, phantom="cyl200", seed=1004),
-    5: ScanConfig("cfg5_head256_tvgd", Grid(256, 256, 64), m=20_000_000, n_angles=360, r_hull=110.0,
+    5: ScanConfig("head256_tvgd", Grid(256, 256, 64), m=20_000_000, n_angles=360, r_hull=110.0,
                   block=6400, lam=0.1, n_iter=20, phantom="head256", order="angle_slab", seed=1005),
     # continuous gantry rotation (as in the paper's scanner data, Section IV-A)
     # on the 200x200x32 geometry, protons sorted into 180 angle bins, then by

@@ -47,7 +47,7 @@ def table_of(h):
 
 @pytest.mark.parametrize("cfg", [1, 2, 3, "tiny"])
 def test_library_table_matches_oracle(cfg):
-    c = synth.CONFIGS[cfg]
+    c = synth.WORKLOADS[cfg]
     st, h = plan_for(c.grid, c.mlp)
     assert st == 0
     got = table_of(h)

@@ -26,7 +26,7 @@ _scans = {}
 
 def scan(cfg, m=None):
     if (cfg, m) not in _scans:
-        _scans[(cfg, m)] = synth.make_scan(synth.CONFIGS[cfg], m=m)
+        _scans[(cfg, m)] = synth.make_scan(synth.WORKLOADS[cfg], m=m)
     return _scans[(cfg, m)]
 
 
@@ -52,7 +52,7 @@ def image_tol(geo, ref):
 def test_sinogram_matches_oracle(cfg, m, n_ang, shuffle):
     sc = scan(cfg, m)
     g = geom_of(sc, n_ang)
-    say(f"fbp sinogram cfg{cfg} m={sc.m} geom={g} shuffled={shuffle}")
+    say(f"fbp sinogram {sc.cfg.name} m={sc.m} geom={g} shuffled={shuffle}")
     prot, bb = sc.protons, sc.b
     if shuffle:
         perm = np.random.default_rng(4).permutation(sc.m)
@@ -161,7 +161,7 @@ def test_ragged_grid():
 
 def test_drop_from_the_fbp_image_matches_oracle():
     oracle.build(force=False)
-    c = synth.CONFIGS[1]
+    c = synth.WORKLOADS[1]
     sc = scan(1, 40000)
     g = geom_of(sc, 90)
     plan = api.Plan(sc.grid, sc.mlp, DEV)

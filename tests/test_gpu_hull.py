@@ -34,7 +34,7 @@ _scans = {}
 
 def scan(cfg, m):
     if (cfg, m) not in _scans:
-        _scans[(cfg, m)] = synth.make_scan(synth.CONFIGS[cfg], m=m)
+        _scans[(cfg, m)] = synth.make_scan(synth.WORKLOADS[cfg], m=m)
     return _scans[(cfg, m)]
 
 
@@ -48,7 +48,7 @@ def setup(cfg, m, radius):
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_hull_traces_bit_exact(cfg):
     sc, plan, pr = setup(cfg, 20000, HULLS[cfg])
-    say(f"hull trace cfg{cfg} R={HULLS[cfg]}")
+    say(f"hull trace {sc.cfg.name} R={HULLS[cfg]}")
     cap = 1024
     vox, ch, nnz = api.pct_mlp_trace(plan, pr, 0, sc.m, max_nnz=cap)
     torch.cuda.synchronize()
@@ -91,7 +91,7 @@ def test_hull_forward_backproject_match_oracle():
 
 
 def test_hull_drop_fp64_matches_oracle():
-    c = synth.CONFIGS[1]
+    c = synth.WORKLOADS[1]
     sc, plan, pr = setup(1, 20000, HULLS[1])
     b = torch.from_numpy(sc.b).to(DEV)
     ref = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=c.block, lam=c.lam, n_iter=2)
@@ -106,7 +106,7 @@ def test_hull_drop_fp64_matches_oracle():
 
 def test_hull_drop_fp32_schedules_bitwise_and_match_oracle():
     from paper_1802_01070_amd._lib import PCT_DROP_NO_TRACE_AHEAD, PCT_DROP_SEPARATE_COMMIT
-    c = synth.CONFIGS[2]
+    c = synth.WORKLOADS[2]
     sc, plan, pr = setup(2, 64000, HULLS[2])
     b = torch.from_numpy(sc.b).to(DEV)
     pr, b = api.pct_order_blocks(plan, pr, b, c.block)
@@ -120,13 +120,13 @@ def test_hull_drop_fp32_schedules_bitwise_and_match_oracle():
     assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
     ref = oracle.drop(sc.grid, sc.mlp, order_np, b.cpu().numpy(), 1.0, block=c.block, lam=c.lam, n_iter=2)
     err = np.max(np.abs(out[0].double().cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0))
-    say(f"  hull FP32 cfg2: {err:.3e}")
+    say(f"  hull FP32 200x200x32: {err:.3e}")
     assert err <= 1e-5
     assert api.pct_device_status(plan) == 0
 
 
 def test_hull_stored_rows_match_oracle():
-    c = synth.CONFIGS[4]
+    c = synth.WORKLOADS[4]
     sc, plan, pr = setup(2, 32000, HULLS[2])
     b = torch.from_numpy(sc.b).to(DEV)
     rows = api.Rows(plan, pr, "f16")

@@ -37,7 +37,7 @@ _scans = {}
 def scan(cfg, m, seed=None):
     key = (cfg, m, seed)
     if key not in _scans:
-        _scans[key] = synth.make_scan(synth.CONFIGS[cfg], m=m, seed=seed)
+        _scans[key] = synth.make_scan(synth.WORKLOADS[cfg], m=m, seed=seed)
     return _scans[key]
 
 
@@ -94,7 +94,7 @@ def test_trace_bit_exact_full_geometry(cfg):
 
 def _hand_scan(rays, grid, mlp):
     pr_np = synth.make_rays(grid, mlp, rays)
-    return synth.Scan(synth.CONFIGS["tiny"], grid, mlp, pr_np, np.zeros(len(rays), np.float32), None)
+    return synth.Scan(synth.WORKLOADS["tiny"], grid, mlp, pr_np, np.zeros(len(rays), np.float32), None)
 
 
 def test_trace_hand_rays_and_edges():
@@ -170,7 +170,7 @@ def test_trace_overflow_and_empty():
                                          (3, 20000, torch.float32)])
 def test_forward_and_norm(cfg, m, dtype):
     sc = scan(cfg, m)
-    say(f"forward parity cfg={cfg} m={m} {dtype}")
+    say(f"forward parity {sc.cfg.name} m={m} {dtype}")
     plan, pr = gpu_setup(sc)
     x_np = sc.x_true() if cfg != 3 else np.random.default_rng(0).uniform(0.2, 1.8, sc.grid.nvox)
     x = torch.from_numpy(x_np).to(DEV, dtype)
@@ -186,7 +186,7 @@ def test_forward_and_norm(cfg, m, dtype):
 @pytest.mark.parametrize("cfg,m,dtype", [(1, 20000, torch.float64), (2, 20000, torch.float32)])
 def test_backproject(cfg, m, dtype):
     sc = scan(cfg, m)
-    say(f"backproject parity cfg={cfg} m={m} {dtype}")
+    say(f"backproject parity {sc.cfg.name} m={m} {dtype}")
     plan, pr = gpu_setup(sc)
     r_np = np.random.default_rng(1).standard_normal(m)
     r = torch.from_numpy(r_np).to(DEV, dtype)
@@ -272,9 +272,9 @@ _drop1_ref = {}
 
 @pytest.mark.parametrize("lanes", [0, 1, 8, 16, 32, 64])
 def test_drop_config1_fp64_full(lanes):
-    cfg = synth.CONFIGS[1]
+    cfg = synth.WORKLOADS[1]
     sc = scan(1, cfg.m)
-    say(f"DROP cfg1 fp64 m={sc.m} iters={cfg.n_iter} lanes={lanes}")
+    say(f"DROP {sc.cfg.name} m={sc.m} iters={cfg.n_iter} lanes={lanes}")
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
     x = torch.ones(sc.grid.nvox, dtype=torch.float64, device=DEV)
@@ -294,9 +294,9 @@ def test_drop_config1_fp64_full(lanes):
                                                ("cont", 64000, 2, 0),
                                                (3, 64000, 1, 0), (3, 64000, 1, 32)])
 def test_drop_fp32(cfg, m, iters, lanes):
-    c = synth.CONFIGS[cfg]
+    c = synth.WORKLOADS[cfg]
     sc = scan(cfg, m)
-    say(f"DROP cfg{cfg} fp32 m={m} iters={iters} lanes={lanes}")
+    say(f"DROP {sc.cfg.name} fp32 m={m} iters={iters} lanes={lanes}")
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
     x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
@@ -340,9 +340,9 @@ def test_drop_full_size_sampled_blocks():
     # the full 10^7-proton scan of the 200x200x32 configuration in the launch
     # configuration the benchmark times; sampled blocks are checked one by one
     # against the oracle started from the GPU's own iterate
-    c = synth.CONFIGS[2]
+    c = synth.WORKLOADS[2]
     sc = scan(2, c.m)
-    say(f"DROP cfg2 full-size sampled blocks m={sc.m}")
+    say(f"DROP 200x200x32 full-size sampled blocks m={sc.m}")
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
     x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
@@ -367,8 +367,8 @@ def test_drop_full_size_head_scan_sampled_blocks():
     # the 5*10^7-proton 256x256x64 head scan (sorted by angle, slab, t_in;
     # block 6400) at full size, ordered inside blocks as the benchmark runs
     # it; sampled blocks checked against the oracle from the GPU's iterate
-    c = synth.CONFIGS[3]
-    say(f"DROP cfg3 full-size sampled blocks: generating {c.m} protons")
+    c = synth.WORKLOADS[3]
+    say(f"DROP 256x256x64 full-size sampled blocks: generating {c.m} protons")
     sc = scan(3, c.m)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
@@ -418,7 +418,7 @@ def test_drop_steep_paths_use_single_lane_fallback():
 
 @pytest.mark.parametrize("chord", ["f16", "bf16"])
 def test_drop_reduced_precision_chords(chord):
-    c = synth.CONFIGS[4]
+    c = synth.WORKLOADS[4]
     sc = scan(4, 32000)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
@@ -441,7 +441,7 @@ def test_drop_reduced_precision_chords(chord):
 # ---------------------------------------------------------------------------
 def test_tv_kernel():
     grid = Grid(16, 12, 5)
-    sc = synth.Scan(synth.CONFIGS["tiny"], grid, MLPModel(u_in=-9, u_out=9), {}, np.zeros(0, np.float32), None)
+    sc = synth.Scan(synth.WORKLOADS["tiny"], grid, MLPModel(u_in=-9, u_out=9), {}, np.zeros(0, np.float32), None)
     plan = api.Plan(grid, sc.mlp, DEV)
     x_np = np.random.default_rng(7).random(grid.nvox).astype(np.float32)
     x = torch.from_numpy(x_np).to(DEV)
@@ -473,7 +473,7 @@ def test_projectfn_gradient_matches_oracle():
 # ---------------------------------------------------------------------------
 def test_graph_replays_match_eager():
     from paper_1802_01070_amd._lib import PCT_DROP_NO_GRAPH
-    c = synth.CONFIGS[1]
+    c = synth.WORKLOADS[1]
     sc = scan(1, 12800)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
@@ -510,7 +510,7 @@ def test_graph_replays_match_eager():
 def test_fp32_drop_is_bitwise_reproducible():
     # the FP32 block accumulator is integer (fixed point + count), so repeated
     # runs and a split resume give identical bits
-    c = synth.CONFIGS[2]
+    c = synth.WORKLOADS[2]
     sc = scan(2, 64000)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
@@ -536,7 +536,7 @@ def test_fused_commit_is_bitwise_the_separate_schedule():
     # blocks (odd and even, to exercise the ping-pong and rotations), any
     # starting block, graph or per-block launches, and repeated sweeps
     from paper_1802_01070_amd._lib import PCT_DROP_NO_GRAPH, PCT_DROP_SEPARATE_COMMIT
-    c = synth.CONFIGS[2]
+    c = synth.WORKLOADS[2]
     sc = scan(2, 64000)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
@@ -575,7 +575,7 @@ def test_traced_ahead_schedule_is_bitwise_the_fused_one():
     # any block range, graph or per-block launches, repeated sweeps, and rows
     # that overflow a lane's stash (they are walked again)
     from paper_1802_01070_amd._lib import PCT_DROP_NO_GRAPH, PCT_DROP_NO_TRACE_AHEAD, PCT_DROP_SEPARATE_COMMIT
-    c = synth.CONFIGS[2]
+    c = synth.WORKLOADS[2]
     sc = scan(2, 64000)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
@@ -621,7 +621,7 @@ def test_order_blocks_sorted_permutation_and_drop_unchanged():
     # slice, t_in, input position); DROP's block update is a sum over the
     # block's rows, so the FP32 result (order-independent accumulator) must be
     # bitwise the same on the ordered copy, also on a ragged last block
-    c = synth.CONFIGS[2]
+    c = synth.WORKLOADS[2]
     sc = scan(2, 64100)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)

@@ -40,7 +40,7 @@ _scans = {}
 
 def scan(key, m=None):
     if (key, m) not in _scans:
-        _scans[(key, m)] = synth.make_scan(synth.CONFIGS[key], m=m)
+        _scans[(key, m)] = synth.make_scan(synth.WORKLOADS[key], m=m)
     return _scans[(key, m)]
 
 
@@ -118,7 +118,7 @@ def test_region_select_capacity_and_empty_input():
 
 
 def test_region_select_full_size_counts():
-    c = synth.CONFIGS[2]
+    c = synth.WORKLOADS[2]
     sc = scan(2, c.m)
     say(f"region select full size m={sc.m}")
     plan = api.Plan(sc.grid, sc.mlp, DEV)

@@ -32,7 +32,7 @@ _scans = {}
 
 def scan(cfg, m):
     if (cfg, m) not in _scans:
-        _scans[(cfg, m)] = synth.make_scan(synth.CONFIGS[cfg], m=m)
+        _scans[(cfg, m)] = synth.make_scan(synth.WORKLOADS[cfg], m=m)
     return _scans[(cfg, m)]
 
 
@@ -48,7 +48,7 @@ def stored_values(rows):
 @pytest.mark.parametrize("chord", ["f32", "f16", "bf16"])
 def test_rows_match_oracle_emission_lists(chord):
     sc = scan(1, 4000)
-    say(f"rows {chord} cfg1 m={sc.m}")
+    say(f"rows {chord} 64x64x4 m={sc.m}")
     plan = api.Plan(sc.grid, sc.mlp, DEV)
     pr = api.Protons(sc.protons, DEV)
     rows = api.Rows(plan, pr, chord)
@@ -85,7 +85,7 @@ def test_rows_match_oracle_emission_lists(chord):
 
 @pytest.mark.parametrize("chord,lanes", [("f16", 0), ("bf16", 32), ("f32", 16)])
 def test_drop_over_stored_rows_matches_oracle(chord, lanes):
-    c = synth.CONFIGS[4]
+    c = synth.WORKLOADS[4]
     sc = scan(4, 32000)
     say(f"stored-row DROP {chord} lanes={lanes} m={sc.m}")
     plan = api.Plan(sc.grid, sc.mlp, DEV)
@@ -139,7 +139,7 @@ def test_stored_rows_full_size_sampled_blocks():
     # 2*10^7 protons on the 200x200x32 grid with FP16 chords (the precision
     # workload at its full size); sampled blocks checked one by one against
     # the oracle started from the GPU's own iterate
-    c = synth.CONFIGS[4]
+    c = synth.WORKLOADS[4]
     sc = scan(4, c.m)
     say(f"stored rows full size m={sc.m}")
     plan = api.Plan(sc.grid, sc.mlp, DEV)

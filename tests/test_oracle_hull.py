@@ -27,7 +27,7 @@ def beam_to_lab(u, t, v, phi):
 
 
 def test_hull_crossings_lie_on_the_circle_and_the_tracks():
-    sc = synth.make_scan(synth.CONFIGS[1], m=400)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=400)
     m = sc.mlp
     R = 24.0
     oracle.set_hull(R, 0.5, -0.25)
@@ -55,7 +55,7 @@ def test_hull_crossings_lie_on_the_circle_and_the_tracks():
 
 
 def test_hull_containing_the_trackers_is_the_tracker_path():
-    sc = synth.make_scan(synth.CONFIGS[1], m=300)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=300)
     ref_v, ref_c, ref_n = oracle.trace(sc.grid, sc.mlp, sc.protons)
     oracle.set_hull(1.0e4)
     v, c, n = oracle.trace(sc.grid, sc.mlp, sc.protons)
@@ -68,7 +68,7 @@ def test_hull_containing_the_trackers_is_the_tracker_path():
 
 
 def test_mlp_part_is_the_mlp_between_the_hull_crossings():
-    sc = synth.make_scan(synth.CONFIGS[1], m=200)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=200)
     m = sc.mlp
     oracle.set_hull(22.0)
     checked = 0

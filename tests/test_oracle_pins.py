@@ -266,7 +266,7 @@ def _brute_row(grid, mlp, pr, i):
 
 
 def test_walk_equals_brute_force_clipping():
-    cfg = synth.CONFIGS["tiny"]
+    cfg = synth.WORKLOADS["tiny"]
     sc = synth.make_scan(cfg, m=300)
     for i in range(0, 300, 7):
         vox, a, _ = oracle.row(sc.grid, sc.mlp, sc.protons, i)
@@ -278,7 +278,7 @@ def test_walk_equals_brute_force_clipping():
 
 
 def test_walk_sum_is_clipped_polyline_length():
-    sc = synth.make_scan(synth.CONFIGS[1], m=200)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=200)
     lo, hi = sc.grid.lo, sc.grid.hi
     for i in range(0, 200, 13):
         P = oracle.vertices(sc.mlp, sc.protons, i)
@@ -311,7 +311,7 @@ def test_reentry_adds_chords():
 # operators
 # ---------------------------------------------------------------------------
 def test_forward_backproject_adjoint():
-    sc = synth.make_scan(synth.CONFIGS[1], m=3000)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=3000)
     rng = np.random.default_rng(5)
     x = rng.random(sc.grid.nvox)
     r = rng.standard_normal(sc.m)
@@ -321,7 +321,7 @@ def test_forward_backproject_adjoint():
 
 
 def test_forward_of_ones_is_clipped_length():
-    sc = synth.make_scan(synth.CONFIGS[1], m=50)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=50)
     y, n2, nd = oracle.forward(sc.grid, sc.mlp, sc.protons, np.ones(sc.grid.nvox))
     for i in range(0, 50, 7):
         _, ch, nnz = oracle.trace(sc.grid, sc.mlp, sc.protons, i, 1)
@@ -335,7 +335,7 @@ def test_forward_of_ones_is_clipped_length():
 # DROP
 # ---------------------------------------------------------------------------
 def test_drop_block_of_one_is_kaczmarz_projection():
-    sc = synth.make_scan(synth.CONFIGS[1], m=40)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=40)
     rng = np.random.default_rng(1)
     x0 = rng.random(sc.grid.nvox) + 0.5
     for i in (0, 11, 29):
@@ -378,7 +378,7 @@ def _dense_rows(sc, lo, hi):
 def test_drop_equals_matrix_form():
     # DROP in matrix form per block: x <- x + lam * diag(1/s) A_t^T W (b_t - A_t x),
     # W = diag(1/||a_i||^2), s_j = number of nonzeros in column j of A_t
-    sc = synth.make_scan(synth.CONFIGS["tiny"], m=600)
+    sc = synth.make_scan(synth.WORKLOADS["tiny"], m=600)
     B, lam = 50, 0.7
     A = _dense_rows(sc, 0, sc.m)
     b = sc.b.astype(np.float64)
@@ -397,7 +397,7 @@ def test_drop_equals_matrix_form():
 
 
 def test_drop_recovers_exact_solution_on_consistent_data():
-    sc = synth.make_scan(synth.CONFIGS["tiny"], m=20000)
+    sc = synth.make_scan(synth.WORKLOADS["tiny"], m=20000)
     A = _dense_rows(sc, 0, 4000)
     assert np.linalg.matrix_rank(A) == sc.grid.nvox          # full column rank
     rng = np.random.default_rng(3)
@@ -413,7 +413,7 @@ def test_drop_recovers_exact_solution_on_consistent_data():
 
 
 def test_drop_block_range_resume_is_exact():
-    sc = synth.make_scan(synth.CONFIGS[1], m=20000)
+    sc = synth.make_scan(synth.WORKLOADS[1], m=20000)
     full = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=3200, lam=0.1, n_iter=1)
     x = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=3200, lam=0.1, n_iter=1, blk_begin=0, blk_end=3)
     x = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, x, block=3200, lam=0.1, n_iter=1, blk_begin=3)
@@ -471,7 +471,7 @@ def test_tv_gradient_central_differences():
 
 
 def test_quadratic_gradient_central_differences():
-    sc = synth.make_scan(synth.CONFIGS["tiny"], m=2000)
+    sc = synth.make_scan(synth.WORKLOADS["tiny"], m=2000)
     rng = np.random.default_rng(4)
     x = rng.random(sc.grid.nvox) + 0.5
     beta = 0.0

@@ -26,7 +26,7 @@ _scans = {}
 
 def scan(key, m=None):
     if (key, m) not in _scans:
-        _scans[(key, m)] = synth.make_scan(synth.CONFIGS[key], m=m)
+        _scans[(key, m)] = synth.make_scan(synth.WORKLOADS[key], m=m)
     return _scans[(key, m)]
 
 
