@@ -256,6 +256,40 @@ int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, doubl
 int pct_order_blocks(const pct_plan *plan, const pct_protons *p, const float *b, int64_t block,
                      const pct_protons_buf *out, float *b_out, void *stream);
 
+/* ---- angle-bin sort of acquisition-order scans (Section IV-A) -------------
+ * The paper reconstructs a scan taken with continuous gantry rotation; its
+ * records arrive in acquisition order.  pct_sort_scan groups them for the
+ * block-iterative solve: a stable sort by the key (a, s, t_in) with
+ *   a = floor(phi / dphi + 1/2) mod n_angles, dphi = 2 pi / n_angles, in FP64
+ *       from the FP32 gantry angle (the angle bin of the FBP entry points);
+ *   s = floor((v_in - z0) / slab_mm) in FP64, clamped to [0, n_slabs - 1],
+ *       z0 the grid's lower z edge, n_slabs = ceil(nz pz / slab_mm);
+ *   t_in compared as a number (-0 equals +0);
+ * records with equal keys keep their input order, and a record whose gantry
+ * angle, v_in or t_in is not finite goes after all others, in input order.
+ * The result is unique (bit-exact whatever the launch shape).  Needs
+ * 1 <= n_angles <= 4096, slab_mm > 0 and finite with n_slabs <= 4096,
+ * reserved = 0. */
+typedef struct {
+    int32_t n_angles;
+    int32_t reserved;   /* must be 0 */
+    double slab_mm;
+} pct_sort_opts;
+
+/* Device workspace for pct_sort_scan on n records: 24 n bytes plus about
+ * n / 16 bytes of digit counts. */
+int pct_sort_scan_workspace_size(int64_t n, size_t *bytes);
+
+/* Writes the records (and b, if not NULL) to out in the order above, and, if
+ * perm is not NULL, perm[j] = input position of output record j (device
+ * int64[n]).  Needs p->n < 2^31, out->capacity >= p->n, b_out when b is given;
+ * out, b_out and perm must not alias the input or each other.  ws: device,
+ * 256-byte aligned, at least pct_sort_scan_workspace_size(p->n) bytes, used
+ * as scratch.  Host-synchronous validation, asynchronous on `stream`. */
+int pct_sort_scan(const pct_plan *plan, const pct_protons *p, const float *b, const pct_sort_opts *opts,
+                  const pct_protons_buf *out, float *b_out, int64_t *perm, void *ws, size_t ws_bytes,
+                  void *stream);
+
 /* ---- stored rows (precision form) ----------------------------------------
  * The precision form lets the chord lengths be stored rather than recomputed.
  * With 288 GB of HBM the rows of the scans here fit (10^7 protons x ~257

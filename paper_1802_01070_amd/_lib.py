@@ -29,7 +29,7 @@ EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan
            "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
            "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows",
            "pct_order_blocks", "pct_plan_set_hull", "pct_fbp_workspace_size", "pct_fbp_sinogram", "pct_fbp_filter",
-           "pct_fbp_backproject", "pct_fbp")
+           "pct_fbp_backproject", "pct_fbp", "pct_sort_scan_workspace_size", "pct_sort_scan")
 
 
 class PctError(RuntimeError):
@@ -67,6 +67,10 @@ class pct_rows(C.Structure):
 
 class pct_fbp_geom(C.Structure):
     _fields_ = [("n_angles", C.c_int32), ("n_t", C.c_int32), ("t0", C.c_double), ("dt", C.c_double)]
+
+
+class pct_sort_opts(C.Structure):
+    _fields_ = [("n_angles", C.c_int32), ("reserved", C.c_int32), ("slab_mm", C.c_double)]
 
 
 class pct_drop_opts(C.Structure):
@@ -118,6 +122,9 @@ def lib() -> C.CDLL:
             "pct_fbp_filter": ([vp, P(pct_fbp_geom), vp, vp, vp], C.c_int),
             "pct_fbp_backproject": ([vp, P(pct_fbp_geom), vp, vp, i32, vp], C.c_int),
             "pct_fbp": ([vp, P(pct_fbp_geom), P(pct_protons), vp, vp, i32, vp, sz, vp], C.c_int),
+            "pct_sort_scan_workspace_size": ([i64, P(sz)], C.c_int),
+            "pct_sort_scan": ([vp, P(pct_protons), vp, P(pct_sort_opts), P(pct_protons_buf), vp, vp, vp, sz, vp],
+                              C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

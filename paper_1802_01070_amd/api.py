@@ -331,6 +331,31 @@ def pct_order_blocks(plan: Plan, p: Protons, b: Optional[torch.Tensor], block: i
     return Protons(bufs, device=dev), b_out
 
 
+def pct_sort_scan(plan: Plan, p: Protons, b: Optional[torch.Tensor], n_angles: int, slab_mm: float,
+                  with_perm: bool = False):
+    """Copy of an acquisition-order scan sorted into angle bins: stable by
+    (angle bin, slab of v_in, t_in), non-finite records last.  Returns
+    (Protons, b or None, perm or None) with perm[j] the input position of
+    output record j."""
+    dev = plan.device
+    nbytes = C.c_size_t()
+    check(lib().pct_sort_scan_workspace_size(int(p.n), C.byref(nbytes)), "pct_sort_scan_workspace_size")
+    ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+    ws_ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    bufs = {k: torch.empty(p.n, dtype=torch.float32, device=dev) for k in FIELDS}
+    b_out = torch.empty(p.n, dtype=torch.float32, device=dev) if b is not None else None
+    perm = torch.empty(p.n, dtype=torch.int64, device=dev) if with_perm else None
+    out = _lib.make_protons_buf({k: v.data_ptr() for k, v in bufs.items()}, p.n)
+    bp = _dev(b, "b", dtype=torch.float32, numel=p.n) if b is not None else None
+    opts = _lib.pct_sort_opts(int(n_angles), 0, float(slab_mm))
+    st = lib().pct_sort_scan(plan.handle, C.byref(p.s), bp, C.byref(opts), C.byref(out),
+                             C.c_void_p(b_out.data_ptr()) if b_out is not None else None,
+                             C.c_void_p(perm.data_ptr()) if perm is not None else None, C.c_void_p(ws_ptr),
+                             int(nbytes.value), _stream(dev))
+    check(st, "pct_sort_scan")
+    return Protons(bufs, device=dev), b_out, perm
+
+
 def pct_select_slices(plan: Plan, src: torch.Tensor, src_z0: int, dst: torch.Tensor, dst_z0: int, z_first: int,
                       z_count: int):
     code = _dtype_code(src)

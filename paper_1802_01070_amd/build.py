@@ -10,8 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpct.so")
-SOURCES = ["pct_api.cpp", "pct_kernels.hip", "pct_fbp.hip"]
-HEADERS = ["pct_internal.h", "pct_path.hpp"]
+SOURCES = ["pct_api.cpp", "pct_kernels.hip", "pct_fbp.hip", "pct_sort.hip"]
+HEADERS = ["pct_internal.h", "pct_path.hpp", "pct_sort.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

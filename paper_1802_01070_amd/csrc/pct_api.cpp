@@ -7,6 +7,7 @@
 #include <new>
 
 #include "pct_internal.h"
+#include "pct_sort.h"
 
 namespace pct {
 
@@ -530,6 +531,61 @@ int pct_order_blocks(const pct_plan *plan, const pct_protons *p, const float *b,
     ProtonsBufDev o{out->t_in, out->v_in, out->th_in, out->ph_in, out->t_out, out->v_out, out->th_out, out->ph_out,
                     out->gantry};
     return hip_status(launch_order_blocks(*plan, protons_dev(p), p->n, b, block, o, b ? b_out : nullptr, stream));
+}
+
+static int sort_setup(const pct_plan *plan, const pct_sort_opts *o, SortDev &s)
+{
+    if (!plan || !o) return PCT_ERR_INVALID_ARG;
+    if (o->n_angles < 1 || o->n_angles > kSortMaxAngles || o->reserved != 0) return PCT_ERR_INVALID_ARG;
+    if (!(o->slab_mm > 0.0) || !std::isfinite(o->slab_mm)) return PCT_ERR_INVALID_ARG;
+    const double ns = std::ceil(double(plan->grid.nz) * plan->grid.pitch[2] / o->slab_mm);
+    if (!(ns >= 1.0) || ns > double(kSortMaxSlabs)) return PCT_ERR_INVALID_ARG;
+    auto bit_width = [](uint32_t v) {
+        int w = 0;
+        while (v) {
+            ++w;
+            v >>= 1;
+        }
+        return w;
+    };
+    s.n_angles = o->n_angles;
+    s.n_slabs = int32_t(ns);
+    s.bits_s = bit_width(uint32_t(s.n_slabs - 1));
+    s.passes = (32 + s.bits_s + bit_width(uint32_t(s.n_angles)) + 7) / 8;
+    s.dphi = 2.0 * M_PI / double(o->n_angles);
+    s.z0 = plan->grid.origin[2];
+    s.slab = o->slab_mm;
+    return PCT_OK;
+}
+
+int pct_sort_scan_workspace_size(int64_t n, size_t *bytes)
+{
+    if (!bytes || n < 0 || n > kSortMaxRecords) return PCT_ERR_INVALID_ARG;
+    *bytes = sort_layout(n).total;
+    return PCT_OK;
+}
+
+int pct_sort_scan(const pct_plan *plan, const pct_protons *p, const float *b, const pct_sort_opts *opts,
+                  const pct_protons_buf *out, float *b_out, int64_t *perm, void *ws, size_t ws_bytes, void *stream)
+{
+    SortDev s;
+    int st = sort_setup(plan, opts, s);
+    if (st) return st;
+    st = check_protons(p);
+    if (st) return st;
+    if (!out || p->n > kSortMaxRecords) return PCT_ERR_INVALID_ARG;
+    if (p->n == 0) return PCT_OK;
+    if (out->capacity < p->n) return PCT_ERR_INVALID_ARG;
+    float *ptrs[9] = {out->t_in, out->v_in, out->th_in, out->ph_in, out->t_out, out->v_out, out->th_out, out->ph_out,
+                      out->gantry};
+    for (float *q : ptrs)
+        if (!q) return PCT_ERR_INVALID_ARG;
+    if (b && !b_out) return PCT_ERR_INVALID_ARG;
+    const SortLayout L = sort_layout(p->n);
+    if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255u)) return PCT_ERR_WORKSPACE;
+    ProtonsBufDev o{out->t_in, out->v_in, out->th_in, out->ph_in, out->t_out, out->v_out, out->th_out, out->ph_out,
+                    out->gantry};
+    return hip_status(launch_sort_scan(s, protons_dev(p), p->n, b, o, b ? b_out : nullptr, perm, ws, stream));
 }
 
 int pct_region_layout(int32_t nz, int32_t n_regions, int32_t halo, int32_t *z_lo, int32_t *z_hi, int32_t *core_lo,

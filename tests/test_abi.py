@@ -345,3 +345,41 @@ def test_fbp_calls_validate(plan):
     assert st == 0
     assert L.pct_fbp_workspace_size(h, C.byref(big), C.byref(sz)) == -1
     L.pct_plan_destroy(h)
+
+
+def test_sort_scan_validates(plan):
+    # plan: 8 x 8 x 2 grid of 1 mm voxels.  Every call below fails validation
+    # on the host, so nothing is launched.
+    L = _lib.lib()
+    O = _lib.pct_sort_opts
+    sz = C.c_size_t()
+    align = lambda v: (v + 255) // 256 * 256
+    assert L.pct_sort_scan_workspace_size(100, C.byref(sz)) == 0
+    assert sz.value == 2 * align(800) + 2 * align(400) + align(4 * 256) + align(4)
+    assert L.pct_sort_scan_workspace_size(0, C.byref(sz)) == 0 and sz.value == 0
+    assert L.pct_sort_scan_workspace_size(-1, C.byref(sz)) == -1
+    assert L.pct_sort_scan_workspace_size(1 << 31, C.byref(sz)) == -1
+    assert L.pct_sort_scan_workspace_size(100, None) == -1
+    p = fake_protons(100)
+    buf = _lib.make_protons_buf({k: 0x9000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, 100)
+    small = _lib.make_protons_buf({k: 0x9000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, 99)
+    ws = C.c_void_p(0x7F0000000000)
+    wsb = 2 * align(800) + 2 * align(400) + align(4 * 256) + align(4)
+    good = O(90, 0, 0.5)
+    for bad in (O(0, 0, 0.5), O(4097, 0, 0.5), O(90, 1, 0.5), O(90, 0, 0.0), O(90, 0, -1.0), O(90, 0, float("nan")),
+                O(90, 0, float("inf")), O(90, 0, 2.0 / 4097)):
+        assert L.pct_sort_scan(plan, C.byref(p), None, C.byref(bad), C.byref(buf), None, None, ws, wsb, None) == -1
+    assert L.pct_sort_scan(plan, C.byref(p), None, None, C.byref(buf), None, None, ws, wsb, None) == -1
+    assert L.pct_sort_scan(None, C.byref(p), None, C.byref(good), C.byref(buf), None, None, ws, wsb, None) == -1
+    assert L.pct_sort_scan(plan, C.byref(p), None, C.byref(good), None, None, None, ws, wsb, None) == -1
+    assert L.pct_sort_scan(plan, C.byref(p), None, C.byref(good), C.byref(small), None, None, ws, wsb, None) == -1
+    assert L.pct_sort_scan(plan, C.byref(p), C.c_void_p(0xA000), C.byref(good), C.byref(buf), None, None, ws, wsb,
+                           None) == -1                                                         # b without b_out
+    # workspace missing, too small, misaligned
+    assert L.pct_sort_scan(plan, C.byref(p), None, C.byref(good), C.byref(buf), None, None, None, wsb, None) == -2
+    assert L.pct_sort_scan(plan, C.byref(p), None, C.byref(good), C.byref(buf), None, None, ws, wsb - 1, None) == -2
+    assert L.pct_sort_scan(plan, C.byref(p), None, C.byref(good), C.byref(buf), None, None,
+                           C.c_void_p(0x7F0000000010), wsb, None) == -2
+    # too many records
+    big = fake_protons(1 << 31)
+    assert L.pct_sort_scan(plan, C.byref(big), None, C.byref(good), C.byref(buf), None, None, ws, wsb, None) == -1
