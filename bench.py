@@ -32,6 +32,7 @@ Two more workloads, each printing its own JSON line:
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -558,6 +559,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per proton in the block kernel (0: automatic)")
     ap.add_argument("--no-drop-compare", action="store_true",
                     help="--config fbp: skip the DROP sweeps from x0 = 1 and from the FBP image")
+    ap.add_argument("--host-sort", action="store_true",
+                    help="continuous-rotation scans: take the generator's angle-bin order instead of the device sort")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -584,9 +587,13 @@ def main():
     key = int(args.config) if args.config.isdigit() else args.config
     cfg = synth.WORKLOADS[key]
     m = args.protons or cfg.m
+    # a continuous-rotation scan arrives in acquisition order and is sorted
+    # into angle bins on the device (pct_sort_scan); --host-sort takes the
+    # generator's sorted copy instead
+    device_sort = cfg.continuous_angles and cfg.order == "angle_slab" and not args.host_sort
     log(f"[bench] generating {cfg.name}: {m} protons")
     t0 = time.perf_counter()
-    sc = synth.make_scan(cfg, m=m)
+    sc = synth.make_scan(cfg.with_(order="acquisition") if device_sort else cfg, m=m)
     log(f"[bench] generated {cfg.name}: {m} protons in {time.perf_counter() - t0:.1f} s")
     dev = "cuda:0"
     plan = api.Plan(sc.grid, sc.mlp, dev)
@@ -597,6 +604,17 @@ def main():
     vdtype = torch.float64 if cfg.value_type == "f64" else torch.float32
     x = torch.ones(sc.grid.nvox, dtype=vdtype, device=dev)
     torch.cuda.synchronize()
+
+    sort_ms = None
+    if device_sort:
+        api.pct_sort_scan(plan, pr, b, cfg.n_angles, cfg.slab_mm)        # first call: allocator warm-up
+        box = {}
+        sort_ms = time_events(lambda: box.setdefault("s", api.pct_sort_scan(plan, pr, b, cfg.n_angles, cfg.slab_mm)))
+        pr, b, _ = box["s"]
+        # the CPU-baseline sample reads the records the device sorted
+        sc = dataclasses.replace(sc, protons={k: pr.t[k].cpu().numpy() for k in synth.FIELDS}, b=b.cpu().numpy())
+        log(f"[bench] sorted {m} acquisition-order records into {cfg.n_angles} angle bins on the device in "
+            f"{sort_ms:.2f} ms")
 
     sum_nnz = count_nonzeros(api, plan, pr)
     order_ms = None
@@ -696,6 +714,9 @@ def main():
             "order_inside_blocks": "acquisition" if order_ms is None else "entry slice, t_in (pct_order_blocks)",
             "hull_radius_mm": args.hull or None,
             "order_ms_once": order_ms,
+            "angle_bins": ("device sort of the acquisition-order scan (pct_sort_scan: angle bin, 4 mm slab of "
+                           "v_in, t_in)" if device_sort else "generator order"),
+            "angle_sort_ms_once": sort_ms,
         },
         "roofline": {
             "bound": "hbm",
