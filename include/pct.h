@@ -276,8 +276,9 @@ typedef struct {
     double slab_mm;
 } pct_sort_opts;
 
-/* Device workspace for pct_sort_scan on n records: 24 n bytes plus about
- * n / 16 bytes of digit counts. */
+/* Device workspace for pct_sort_scan on n records: 64 n bytes (keys,
+ * positions and a packed copy of the records) plus about n / 16 bytes of
+ * digit counts. */
 int pct_sort_scan_workspace_size(int64_t n, size_t *bytes);
 
 /* Writes the records (and b, if not NULL) to out in the order above, and, if

@@ -22,7 +22,9 @@ struct SortDev {
 
 // Workspace layout (byte offsets, each 256-byte aligned)
 struct SortLayout {
-    size_t keys0, keys1, idx0, idx1, hist, part, total;
+    size_t keys0, keys1, idx0, idx1, hist, part;
+    size_t rec;         // n packed records of 10 floats (9 fields, then b)
+    size_t total;
     int64_t n_tiles;    // tiles of kSortTile records
     int64_t n_hist;     // 256 * n_tiles digit counts
     int64_t n_parts;    // partial sums of the count scan

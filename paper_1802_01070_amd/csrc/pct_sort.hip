@@ -10,7 +10,8 @@
 // and the (key, position) pairs go through a least-significant-digit radix
 // sort with 8-bit digits, one pass per digit the key uses:
 //
-//   k_sort_keys         one thread per record: the key and the position
+//   k_sort_keys         one thread per record: the key, the position, and a
+//                       packed 40-byte copy of the record (9 fields and b)
 //   k_sort_hist         one workgroup per tile of 4096 pairs: digit counts in
 //                       LDS, written digit-major (count of digit d in tile g at
 //                       d * n_tiles + g), so that one exclusive scan of the
@@ -23,7 +24,10 @@
 //                       bit), the counts of earlier waves and rounds from LDS;
 //                       equal digits keep their input order (stable)
 //   k_sort_gather       one thread per output record: copy the record from its
-//                       input position
+//                       input position, read from the packed copy (the angles
+//                       of a continuous scan are uniform in acquisition order,
+//                       so sources are random: one or two cache lines per
+//                       record instead of one per field)
 //
 // The sort is integer work: the output is unique and bit-exact whatever the
 // launch shape.
@@ -67,13 +71,20 @@ __device__ inline unsigned long long sort_key(const SortDev &s, float phi32, flo
            static_cast<unsigned long long>(u);
 }
 
-__global__ void __launch_bounds__(kSortWG) k_sort_keys(ProtonsDev p, int64_t n, SortDev s, unsigned long long *key,
-                                                       uint32_t *idx)
+__global__ void __launch_bounds__(kSortWG) k_sort_keys(ProtonsDev p, const float *b, int64_t n, SortDev s,
+                                                       unsigned long long *key, uint32_t *idx, float2 *rec)
 {
     const int64_t i = int64_t(blockIdx.x) * kSortWG + threadIdx.x;
     if (i >= n) return;
-    key[i] = sort_key(s, p.gantry[i], p.v_in[i], p.t_in[i]);
+    const float t = p.t_in[i], v = p.v_in[i], phi = p.gantry[i];
+    key[i] = sort_key(s, phi, v, t);
     idx[i] = uint32_t(i);
+    float2 *r = rec + 5 * i;
+    r[0] = make_float2(t, v);
+    r[1] = make_float2(p.th_in[i], p.ph_in[i]);
+    r[2] = make_float2(p.t_out[i], p.v_out[i]);
+    r[3] = make_float2(p.th_out[i], p.ph_out[i]);
+    r[4] = make_float2(phi, b ? b[i] : 0.0f);
 }
 
 __global__ void __launch_bounds__(kSortWG) k_sort_hist(const unsigned long long *key, int64_t n, int shift,
@@ -212,23 +223,25 @@ __global__ void __launch_bounds__(kSortWG) k_sort_scatter(const unsigned long lo
     }
 }
 
-__global__ void __launch_bounds__(kSortWG) k_sort_gather(ProtonsDev p, const float *b, int64_t n, const uint32_t *idx,
+__global__ void __launch_bounds__(kSortWG) k_sort_gather(const float2 *rec, int64_t n, const uint32_t *idx,
                                                          ProtonsBufDev o, float *b_out, int64_t *perm)
 {
     const int64_t j = int64_t(blockIdx.x) * kSortWG + threadIdx.x;
     if (j >= n) return;
     const int64_t i = idx[j];
     if (i >= n) return;                 // idx is a permutation of 0 .. n-1
-    o.t_in[j] = p.t_in[i];
-    o.v_in[j] = p.v_in[i];
-    o.th_in[j] = p.th_in[i];
-    o.ph_in[j] = p.ph_in[i];
-    o.t_out[j] = p.t_out[i];
-    o.v_out[j] = p.v_out[i];
-    o.th_out[j] = p.th_out[i];
-    o.ph_out[j] = p.ph_out[i];
-    o.gantry[j] = p.gantry[i];
-    if (b_out) b_out[j] = b[i];
+    const float2 *r = rec + 5 * i;
+    const float2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
+    o.t_in[j] = r0.x;
+    o.v_in[j] = r0.y;
+    o.th_in[j] = r1.x;
+    o.ph_in[j] = r1.y;
+    o.t_out[j] = r2.x;
+    o.v_out[j] = r2.y;
+    o.th_out[j] = r3.x;
+    o.ph_out[j] = r3.y;
+    o.gantry[j] = r4.x;
+    if (b_out) b_out[j] = r4.y;
     if (perm) perm[j] = i;
 }
 
@@ -253,6 +266,8 @@ SortLayout sort_layout(int64_t n)
     o += align256(size_t(L.n_hist) * 4);
     L.part = o;
     o += align256(size_t(L.n_parts) * 4);
+    L.rec = o;
+    o += align256(size_t(n) * 40);
     L.total = o;
     return L;
 }
@@ -270,8 +285,9 @@ int launch_sort_scan(const SortDev &s, const ProtonsDev &p, int64_t n, const flo
     auto *i1 = reinterpret_cast<uint32_t *>(w + L.idx1);
     auto *hist = reinterpret_cast<uint32_t *>(w + L.hist);
     auto *part = reinterpret_cast<uint32_t *>(w + L.part);
+    auto *rec = reinterpret_cast<float2 *>(w + L.rec);
     const unsigned blocks = unsigned((n + kSortWG - 1) / kSortWG);
-    hipLaunchKernelGGL(k_sort_keys, dim3(blocks), dim3(kSortWG), 0, st, p, n, s, k0, i0);
+    hipLaunchKernelGGL(k_sort_keys, dim3(blocks), dim3(kSortWG), 0, st, p, b, n, s, k0, i0, rec);
     for (int pass = 0; pass < s.passes; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_sort_hist, dim3(unsigned(L.n_tiles)), dim3(kSortWG), 0, st, k0, n, shift, L.n_tiles,
@@ -285,7 +301,7 @@ int launch_sort_scan(const SortDev &s, const ProtonsDev &p, int64_t n, const flo
         std::swap(k0, k1);
         std::swap(i0, i1);
     }
-    hipLaunchKernelGGL(k_sort_gather, dim3(blocks), dim3(kSortWG), 0, st, p, b, n, i0, o, b_out, perm);
+    hipLaunchKernelGGL(k_sort_gather, dim3(blocks), dim3(kSortWG), 0, st, rec, n, i0, o, b_out, perm);
     return hipGetLastError();
 }
 

@@ -355,7 +355,8 @@ def test_sort_scan_validates(plan):
     sz = C.c_size_t()
     align = lambda v: (v + 255) // 256 * 256
     assert L.pct_sort_scan_workspace_size(100, C.byref(sz)) == 0
-    assert sz.value == 2 * align(800) + 2 * align(400) + align(4 * 256) + align(4)
+    full = 2 * align(800) + 2 * align(400) + align(4 * 256) + align(4) + align(4000)
+    assert sz.value == full
     assert L.pct_sort_scan_workspace_size(0, C.byref(sz)) == 0 and sz.value == 0
     assert L.pct_sort_scan_workspace_size(-1, C.byref(sz)) == -1
     assert L.pct_sort_scan_workspace_size(1 << 31, C.byref(sz)) == -1
@@ -364,7 +365,7 @@ def test_sort_scan_validates(plan):
     buf = _lib.make_protons_buf({k: 0x9000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, 100)
     small = _lib.make_protons_buf({k: 0x9000 + 64 * i for i, k in enumerate(_lib.FIELDS)}, 99)
     ws = C.c_void_p(0x7F0000000000)
-    wsb = 2 * align(800) + 2 * align(400) + align(4 * 256) + align(4)
+    wsb = full
     good = O(90, 0, 0.5)
     for bad in (O(0, 0, 0.5), O(4097, 0, 0.5), O(90, 1, 0.5), O(90, 0, 0.0), O(90, 0, -1.0), O(90, 0, float("nan")),
                 O(90, 0, float("inf")), O(90, 0, 2.0 / 4097)):
