@@ -22,7 +22,9 @@
 //                       order: a lane's rank among the lanes of its wave with
 //                       the same digit comes from 8 ballots (one per digit
 //                       bit), the counts of earlier waves and rounds from LDS;
-//                       equal digits keep their input order (stable)
+//                       equal digits keep their input order (stable).  The
+//                       tile's pairs are staged in LDS in digit order and
+//                       written out as one run per digit
 //   k_sort_gather       one thread per output record: copy the record from its
 //                       input position, read from the packed copy (the angles
 //                       of a continuous scan are uniform in acquisition order,
@@ -177,12 +179,25 @@ __global__ void __launch_bounds__(kSortWG) k_sort_scatter(const unsigned long lo
                                                           unsigned long long *key_out, uint32_t *idx_out)
 {
     __shared__ uint32_t base[256];                  // next output slot of each digit
+    __shared__ uint32_t first[256];                 // output slot of the tile's first pair of each digit
+    __shared__ uint32_t local[256];                 // tile-local start of each digit (pairs in digit order)
     __shared__ uint32_t cnt[kSortWaves][256];       // this round's count per wave and digit
+    __shared__ unsigned long long skey[kSortTile];  // the tile's pairs, staged in digit order
+    __shared__ uint32_t sidx[kSortTile];
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
-    base[t] = off[int64_t(t) * n_tiles + blockIdx.x];
+    // pairs of digit t in this tile: the next offset of the scanned counts
+    // (digit-major) minus this one; the last entry ends at n
+    const int64_t e = int64_t(t) * n_tiles + blockIdx.x;
+    const uint32_t o0 = off[e];
+    const uint32_t o1 = e + 1 < 256 * n_tiles ? off[e + 1] : uint32_t(n);
+    base[t] = o0;
+    first[t] = o0;
     for (int w = 0; w < kSortWaves; ++w) cnt[w][t] = 0;
+    uint32_t tile_total;
+    local[t] = wg_exclusive_scan(o1 - o0, cnt[0], tile_total);   // cnt[0] is scratch here, cleared below
+    cnt[0][t] = 0;
     __syncthreads();
     const int64_t tile0 = int64_t(blockIdx.x) * kSortTile;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -207,9 +222,10 @@ __global__ void __launch_bounds__(kSortWG) k_sort_scatter(const unsigned long lo
         if (valid) {
             uint32_t dst = base[d] + rank;
             for (int w = 0; w < wave; ++w) dst += cnt[w][d];
-            if (int64_t(dst) < n) {
-                key_out[dst] = k;
-                idx_out[dst] = ix;
+            const uint32_t lp = local[d] + (dst - first[d]);
+            if (lp < uint32_t(kSortTile)) {
+                skey[lp] = k;
+                sidx[lp] = ix;
             }
         }
         __syncthreads();
@@ -220,6 +236,17 @@ __global__ void __launch_bounds__(kSortWG) k_sort_scatter(const unsigned long lo
         }
         base[t] += add;
         __syncthreads();
+    }
+    // write the staged pairs out in digit order: consecutive threads write
+    // consecutive slots of each digit's run
+    for (uint32_t q = uint32_t(t); q < tile_total && q < uint32_t(kSortTile); q += kSortWG) {
+        const unsigned long long k = skey[q];
+        const unsigned d = unsigned(k >> shift) & 255u;
+        const uint32_t dst = first[d] + (q - local[d]);
+        if (int64_t(dst) < n) {
+            key_out[dst] = k;
+            idx_out[dst] = sidx[q];
+        }
     }
 }
 
