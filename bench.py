@@ -117,7 +117,7 @@ def count_nonzeros(api, plan, pr, chunk=1 << 20):
     return total
 
 
-def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks, hull=0.0):
+def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks, hull=0.0, mode="none"):
     """FP64 oracle on the first n_blocks blocks of one sweep (from x0 = 1):
     throughput on the host cores and the RSP error of the GPU result on the
     same sample."""
@@ -127,15 +127,28 @@ def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks, hull=0.0):
     m = min(sc.m, n_blocks * cfg.block)
     sub = sc.subset(0, m)
     t0 = time.perf_counter()
-    ref = oracle.drop(sc.grid, sc.mlp, sub.protons, sub.b, 1.0, block=cfg.block, lam=cfg.lam, n_iter=1)
+    ref = oracle.drop(sc.grid, sc.mlp, sub.protons, sub.b, 1.0, block=cfg.block, lam=cfg.lam, n_iter=1, mode=mode)
     dt = time.perf_counter() - t0
     err = np.abs(x_gpu_sample - ref) / np.maximum(np.abs(ref), 1.0)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": m / dt, "unit": "proton-iterations/s", "cores": threads, "kind": "oracle",
         "sample": f"first {n_blocks} blocks ({m} protons) of one sweep of the same scan, FP64 C oracle, "
-                  f"{dt:.1f} s",
+                  f"{dt:.1f} s" + ("" if mode == "none" else f", chords rounded to {mode}"),
     }, float(err.max()), float(err.mean())
+
+
+def sweep_roofline(ms_per_sweep, T, m, sum_nnz, kernel):
+    """Roofline entry of the block kernel from the time of whole sweeps: the
+    sweep's stream carries the T block launches and two small kernels."""
+    k_ms = ms_per_sweep / T
+    nbytes = (BYTES_PER_PROTON * m + BYTES_PER_NONZERO * sum_nnz) / T
+    gbs = nbytes / (k_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "traffic_source": "counters taken on the FP32-chord 10^7-proton run only",
+            "kernel": kernel, "kernel_avg_us": k_ms * 1e3,
+            "kernel_avg_us_how": "sweeps timed with HIP events on the sweep's stream / block launches",
+            "algorithmic_bytes_per_launch": nbytes}
 
 
 def time_events(fn, reps=1):
@@ -239,6 +252,22 @@ def run_precision(args):
                                    "speedup_incl_build_vs_f32_chords": runs["f32"][1] / (ms + build_ms),
                                    "status": bits}
     f16_ms = runs["f16"][1]
+    sum_nnz = count_nonzeros(api, plan, pr)
+    T = (m + cfg.block - 1) // cfg.block
+    roof = sweep_roofline(f16_ms / n_iter, T, m, sum_nnz,
+                          "k_drop_pipe with FP16 chords (trace ahead, DROP step, commit; chords rounded as traced)")
+    roof["nonzeros_per_proton"] = sum_nnz / m
+    cpu = None
+    cpu_err = None
+    if not args.no_cpu_baseline:
+        nb = min(args.cpu_blocks, T)
+        xs = torch.ones(sc.grid.nvox, dtype=torch.float32, device=dev)
+        api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1, block_end=nb, chord="f16")
+        torch.cuda.synchronize()
+        log(f"[bench] CPU oracle baseline on {nb} blocks (FP16 chords) ...")
+        cpu, emax, emean = cpu_baseline(sc, cfg, xs.double().cpu().numpy(), nb, mode="f16")
+        cpu_err = {"sample": f"first {nb} blocks of one sweep, FP16 chords on both sides", "max": emax,
+                   "mean": emean}
     out = {
         "metric": "proton-iterations/sec (fused MLP+DROP, FP16 chords) at 1 GPU",
         "value": m * n_iter / (f16_ms * 1e-3),
@@ -252,6 +281,9 @@ def run_precision(args):
                                "a_i.x and ||a_i||^2",
                    "reference": "same scan, FP64 iterate and FP64 chords on the GPU",
                    "touched_voxels": int(touched.sum())},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "rsp_err_vs_fp64_oracle": cpu_err,
         "precision": table,
     }
     print(json.dumps(out), flush=True)
@@ -294,6 +326,41 @@ def run_gradient(args):
     bits = api.pct_device_status(plan)
     log(f"[bench] forward {f_ms:.1f} ms, back projection {b_ms:.1f} ms, GD {gd_ms:.0f} ms; "
         f"loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    sum_nnz = count_nonzeros(api, plan, pr)
+    # dominant kernel: k_backproject (one lane per proton: 9 record fields and
+    # r_i in, 40 B; one FP32 atomic per nonzero)
+    bp_bytes = BYTES_PER_PROTON * m + 4.0 * sum_nnz
+    bp_gbs = bp_bytes / (b_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": bp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bp_gbs / HBM_PEAK_GBS,
+            "traffic": None, "traffic_source": "no counter run on this workload",
+            "kernel": "k_backproject (A^T r: MLP trace per proton, one FP32 atomic per nonzero)",
+            "kernel_avg_us": b_ms * 1e3, "kernel_avg_us_how": "HIP events on the stream, mean of 3 launches",
+            "algorithmic_bytes_per_launch": bp_bytes, "nonzeros_per_proton": sum_nnz / m,
+            "forward_kernel_avg_us": f_ms * 1e3,
+            "forward_GBps": (BYTES_PER_PROTON * m + 4.0 * sum_nnz) / (f_ms * 1e-3) / 1e9}
+    cpu = None
+    cpu_err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        ms_ = min(m, 400_000)
+        sub = sc.subset(0, ms_)
+        xt = np.ones(sc.grid.nvox)
+        rt = np.ones(ms_)
+        log(f"[bench] CPU oracle baseline: forward + back projection of {ms_} protons ...")
+        t1 = time.perf_counter()
+        y_ref = oracle.forward(sc.grid, sc.mlp, sub.protons, xt)
+        oracle.backproject(sc.grid, sc.mlp, sub.protons, rt)
+        dt = time.perf_counter() - t1
+        y_gpu = api.pct_forward(plan, api.Protons(sub.protons, dev), x0)
+        y_gpu = (y_gpu[0] if isinstance(y_gpu, tuple) else y_gpu).double().cpu().numpy()
+        yr = np.asarray(y_ref[0] if isinstance(y_ref, tuple) else y_ref, dtype=np.float64)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": ms_ / dt, "unit": "proton-iterations/s", "cores": threads, "kind": "oracle",
+               "sample": f"forward A.x and back projection A^T r of the first {ms_} protons, FP64 C oracle, "
+                         f"{dt:.1f} s (one gradient step per proton)"}
+        rel = np.abs(y_gpu - yr) / np.maximum(np.abs(yr), 1.0)
+        cpu_err = {"sample": f"A.1 of the first {ms_} protons", "max": float(rel.max()), "mean": float(rel.mean())}
     out = {
         "metric": "proton-iterations/sec (TV-regularised gradient descent, forward+backward) at 1 GPU",
         "value": m * n_steps / (gd_ms * 1e-3),
@@ -310,6 +377,9 @@ def run_gradient(args):
         "eta": eta,
         "loss_curve": losses,
         "status": bits,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forward_err_vs_fp64_oracle": cpu_err,
     }
     print(json.dumps(out), flush=True)
 
