@@ -709,15 +709,20 @@ def main():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    # one event after every sweep as well: the median sweep is reported beside
+    # the mean over the timed region
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     e0.record(stream)
     t_host = time.perf_counter()
     for k in range(args.steps):
         api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes)
+        marks[k].record(stream)
         log(f"[bench] step {k + 1}/{args.steps} enqueued")
     e1.record(stream)
     torch.cuda.synchronize()
     t_host = time.perf_counter() - t_host
     ms_total = e0.elapsed_time(e1)
+    step_ms = [e0.elapsed_time(marks[0])] + [marks[k - 1].elapsed_time(marks[k]) for k in range(1, args.steps)]
     # One more sweep, right after the timed region and on the same stream, with
     # a sample of the block-kernel and commit launches bracketed by HIP events
     # (recorded by the library) to time the dominant kernel itself.
@@ -769,6 +774,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_median": float(np.median(step_ms)),
+        "ms_per_step_min_max": [float(min(step_ms)), float(max(step_ms))],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
