@@ -88,3 +88,28 @@ def test_empty_scan_and_sorted_input_unchanged():
     out = check_sorted(sc.grid, sc.protons, None, 360, 4.0)
     for k in synth.FIELDS:
         assert np.array_equal(out.t[k].cpu().numpy(), sc.protons[k]), k
+
+
+def test_drop_on_the_device_sorted_scan_matches_oracle():
+    # the continuous-rotation path end to end: acquisition-order records,
+    # device sort, within-block ordering, two DROP sweeps; the oracle sorts
+    # the same records with its own ordering and runs its DROP on them
+    import oracle
+    oracle.build(force=False)
+    cfg = synth.WORKLOADS["cont"]
+    sc = synth.make_scan(cfg.with_(order="acquisition"), m=64000)
+    say(f"DROP on the device-sorted {cfg.name} m={sc.m}")
+    plan = api.Plan(sc.grid, sc.mlp, DEV)
+    pr = api.Protons(sc.protons, DEV)
+    b = torch.from_numpy(sc.b).to(DEV)
+    spr, sb, _ = api.pct_sort_scan(plan, pr, b, cfg.n_angles, cfg.slab_mm)
+    spr, sb = api.pct_order_blocks(plan, spr, sb, cfg.block)
+    x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+    api.pct_drop_iterate(plan, spr, sb, x, block=cfg.block, lam=cfg.lam, n_iter=2)
+    torch.cuda.synchronize()
+    opr, ob, _ = O.sort_scan(sc.grid, sc.protons, sc.b, cfg.n_angles, cfg.slab_mm)
+    ref = oracle.drop(sc.grid, sc.mlp, opr, ob, 1.0, block=cfg.block, lam=cfg.lam, n_iter=2)
+    err = np.max(np.abs(x.double().cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0))
+    say(f"  max err {err:.3e}")
+    assert err <= 1e-5
+    assert api.pct_device_status(plan) == 0
