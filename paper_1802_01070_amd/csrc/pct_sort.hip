@@ -74,19 +74,36 @@ __device__ inline unsigned long long sort_key(const SortDev &s, float phi32, flo
 }
 
 __global__ void __launch_bounds__(kSortWG) k_sort_keys(ProtonsDev p, const float *b, int64_t n, SortDev s,
-                                                       unsigned long long *key, uint32_t *idx, float2 *rec)
+                                                       unsigned long long *key, uint32_t *idx, float *rec)
 {
-    const int64_t i = int64_t(blockIdx.x) * kSortWG + threadIdx.x;
-    if (i >= n) return;
-    const float t = p.t_in[i], v = p.v_in[i], phi = p.gantry[i];
-    key[i] = sort_key(s, phi, v, t);
-    idx[i] = uint32_t(i);
-    float2 *r = rec + 5 * i;
-    r[0] = make_float2(t, v);
-    r[1] = make_float2(p.th_in[i], p.ph_in[i]);
-    r[2] = make_float2(p.t_out[i], p.v_out[i]);
-    r[3] = make_float2(p.th_out[i], p.ph_out[i]);
-    r[4] = make_float2(phi, b ? b[i] : 0.0f);
+    // the workgroup's packed records are staged in LDS and written out as
+    // 16-byte stores over its contiguous 10 * 256 floats
+    __shared__ float4 stage[kSortWG * 10 / 4];
+    float *st = reinterpret_cast<float *>(stage);
+    const int64_t i0 = int64_t(blockIdx.x) * kSortWG;
+    const int64_t i = i0 + threadIdx.x;
+    if (i < n) {
+        const float t = p.t_in[i], v = p.v_in[i], phi = p.gantry[i];
+        key[i] = sort_key(s, phi, v, t);
+        idx[i] = uint32_t(i);
+        float *r = st + 10 * threadIdx.x;
+        r[0] = t;
+        r[1] = v;
+        r[2] = p.th_in[i];
+        r[3] = p.ph_in[i];
+        r[4] = p.t_out[i];
+        r[5] = p.v_out[i];
+        r[6] = p.th_out[i];
+        r[7] = p.ph_out[i];
+        r[8] = phi;
+        r[9] = b ? b[i] : 0.0f;
+    }
+    __syncthreads();
+    const int count = int(min<int64_t>(kSortWG, n - i0));     // records of this workgroup
+    const int nf = 10 * count;                                  // floats to write
+    float *out = rec + 10 * i0;                                 // 16-byte aligned: 10 * 256 floats per workgroup
+    for (int q = threadIdx.x; q < nf / 4; q += kSortWG) reinterpret_cast<float4 *>(out)[q] = stage[q];
+    for (int q = (nf / 4) * 4 + threadIdx.x; q < nf; q += kSortWG) out[q] = st[q];
 }
 
 __global__ void __launch_bounds__(kSortWG) k_sort_hist(const unsigned long long *key, int64_t n, int shift,
@@ -250,14 +267,14 @@ __global__ void __launch_bounds__(kSortWG) k_sort_scatter(const unsigned long lo
     }
 }
 
-__global__ void __launch_bounds__(kSortWG) k_sort_gather(const float2 *rec, int64_t n, const uint32_t *idx,
+__global__ void __launch_bounds__(kSortWG) k_sort_gather(const float *rec, int64_t n, const uint32_t *idx,
                                                          ProtonsBufDev o, float *b_out, int64_t *perm)
 {
     const int64_t j = int64_t(blockIdx.x) * kSortWG + threadIdx.x;
     if (j >= n) return;
     const int64_t i = idx[j];
     if (i >= n) return;                 // idx is a permutation of 0 .. n-1
-    const float2 *r = rec + 5 * i;
+    const float2 *r = reinterpret_cast<const float2 *>(rec + 10 * i);
     const float2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
     o.t_in[j] = r0.x;
     o.v_in[j] = r0.y;
@@ -312,7 +329,7 @@ int launch_sort_scan(const SortDev &s, const ProtonsDev &p, int64_t n, const flo
     auto *i1 = reinterpret_cast<uint32_t *>(w + L.idx1);
     auto *hist = reinterpret_cast<uint32_t *>(w + L.hist);
     auto *part = reinterpret_cast<uint32_t *>(w + L.part);
-    auto *rec = reinterpret_cast<float2 *>(w + L.rec);
+    auto *rec = reinterpret_cast<float *>(w + L.rec);
     const unsigned blocks = unsigned((n + kSortWG - 1) / kSortWG);
     hipLaunchKernelGGL(k_sort_keys, dim3(blocks), dim3(kSortWG), 0, st, p, b, n, s, k0, i0, rec);
     for (int pass = 0; pass < s.passes; ++pass) {
