@@ -12,13 +12,13 @@
 //
 //   k_sort_keys         one thread per record: the key, the position, and a
 //                       packed 40-byte copy of the record (9 fields and b)
-//   k_sort_hist         one workgroup per tile of 4096 pairs: digit counts in
+//   k_sort_hist         one workgroup per tile of 2048 pairs: digit counts in
 //                       LDS, written digit-major (count of digit d in tile g at
 //                       d * n_tiles + g), so that one exclusive scan of the
 //                       counts gives every (digit, tile) its output offset
 //   k_sort_count_*      that scan: partial sums of 4096 counts, a one-workgroup
 //                       scan of the partials, then the scan of each segment
-//   k_sort_scatter      one workgroup per tile, 16 rounds of 256 pairs in input
+//   k_sort_scatter      one workgroup per tile, 8 rounds of 256 pairs in input
 //                       order: a lane's rank among the lanes of its wave with
 //                       the same digit comes from 8 ballots (one per digit
 //                       bit), the counts of earlier waves and rounds from LDS;
@@ -48,7 +48,7 @@ namespace {
 
 constexpr int kSortWG = 256;
 constexpr int kSortWaves = kSortWG / 64;
-constexpr int kSortRounds = 16;
+constexpr int kSortRounds = 8;
 constexpr int64_t kSortTile = int64_t(kSortWG) * kSortRounds;   // records per tile
 constexpr int kScanPer = 16;
 constexpr int64_t kScanSeg = int64_t(kSortWG) * kScanPer;       // counts per scan workgroup
