@@ -629,6 +629,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per proton in the block kernel (0: automatic)")
     ap.add_argument("--no-drop-compare", action="store_true",
                     help="--config fbp: skip the DROP sweeps from x0 = 1 and from the FBP image")
+    ap.add_argument("--separate-commit", action="store_true",
+                    help="FP32: the separate schedule (block kernel, then a commit kernel per block)")
     ap.add_argument("--host-sort", action="store_true",
                     help="continuous-rotation scans: take the generator's angle-bin order instead of the device sort")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -641,7 +643,7 @@ def main():
 
     import torch
     from paper_1802_01070_amd import api, synth
-    from paper_1802_01070_amd._lib import PCT_DROP_PROFILE
+    from paper_1802_01070_amd._lib import PCT_DROP_PROFILE, PCT_DROP_SEPARATE_COMMIT
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.config == "4":
@@ -696,11 +698,12 @@ def main():
         pr, b = box["o"]
         log(f"[bench] ordered blocks in {order_ms:.1f} ms")
     T = (m + cfg.block - 1) // cfg.block
+    sched = PCT_DROP_SEPARATE_COMMIT if args.separate_commit else 0
     log(f"[bench] sum of nonzeros {sum_nnz} ({sum_nnz / m:.1f} per proton), {T} blocks per sweep")
 
     # untimed warmup sweeps (the first run also compiles nothing: the library is prebuilt)
     for _ in range(args.warmup):
-        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes)
+        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes, flags=sched)
     torch.cuda.synchronize()
     x.fill_(1.0)
     torch.cuda.synchronize()
@@ -715,7 +718,7 @@ def main():
     e0.record(stream)
     t_host = time.perf_counter()
     for k in range(args.steps):
-        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes)
+        api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes, flags=sched)
         marks[k].record(stream)
         log(f"[bench] step {k + 1}/{args.steps} enqueued")
     e1.record(stream)
@@ -727,7 +730,7 @@ def main():
     # a sample of the block-kernel and commit launches bracketed by HIP events
     # (recorded by the library) to time the dominant kernel itself.
     api.pct_drop_iterate(plan, pr, b, x, block=cfg.block, lam=cfg.lam, n_iter=1, lanes=args.lanes,
-                         flags=PCT_DROP_PROFILE)
+                         flags=PCT_DROP_PROFILE | sched)
     torch.cuda.synchronize()
     bits = api.pct_device_status(plan)
     if bits:
@@ -755,15 +758,15 @@ def main():
     # runs the block kernel and a separate commit
     lanes = args.lanes or (64 if max(sc.grid.nx, sc.grid.ny) >= 160 else 32 if max(sc.grid.nx, sc.grid.ny) >= 64
                            else 16)
-    if vdtype == torch.float32 and lanes == 64 and cfg.block <= 4096:
+    if vdtype == torch.float32 and lanes == 64 and cfg.block <= 4096 and not args.separate_commit:
         kname, kdesc = "k_drop_pipe", ("k_drop_pipe (trace of block t+1 into a row slot, DROP step of block t: "
                                        "a.x + |a|^2 + rho + D-weighted scatter, commit of block t-1)")
-    elif vdtype == torch.float32:
+    elif vdtype == torch.float32 and not args.separate_commit:
         kname, kdesc = "k_drop_fused", ("k_drop_fused (MLP trace + a.x + |a|^2 + rho + D-weighted scatter of "
                                         "block t, commit of block t-1)")
     else:
         kname, kdesc = "k_drop_block", "k_drop_block (MLP trace + a.x + |a|^2 + rho + scatter) + k_drop_commit"
-    traffic, traffic_src = (measured_traffic(cfg.name, kname) if not (args.protons or args.hull)
+    traffic, traffic_src = (measured_traffic(cfg.name, kname) if not (args.protons or args.hull or args.separate_commit)
                             else (None, "counters taken on the default tracker-to-tracker run"))
 
     out = {
@@ -820,7 +823,8 @@ def main():
     if not args.no_cpu_baseline:
         nb = min(args.cpu_blocks, T)
         xs = torch.ones(sc.grid.nvox, dtype=vdtype, device=dev)
-        api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1, block_end=nb, lanes=args.lanes)
+        api.pct_drop_iterate(plan, pr, b, xs, block=cfg.block, lam=cfg.lam, n_iter=1, block_end=nb, lanes=args.lanes,
+                             flags=sched)
         torch.cuda.synchronize()
         log(f"[bench] CPU oracle baseline on {nb} blocks ...")
         cb, emax, emean = cpu_baseline(sc, cfg, xs.double().cpu().numpy(), nb, args.hull)
