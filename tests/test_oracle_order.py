@@ -109,3 +109,37 @@ def test_sorted_and_stable_with_ties_and_edge_records():
     ks = [key(int(i)) for i in perm]
     for j in range(1, n):
         assert ks[j - 1] < ks[j] or (ks[j - 1] == ks[j] and perm[j - 1] < perm[j]), j
+
+
+@pytest.mark.parametrize("mistake", ["no_wrap", "truncate", "no_half", "no_clamp", "bins_by_degrees"])
+def test_hand_example_catches_planted_mistakes(mistake, monkeypatch):
+    # each plausible slip in the angle or slab formula, planted in the oracle
+    # (through the numpy functions it calls, restored after the test),
+    # changes the hand-worked bins or order
+    grid = synth.Grid(4, 4, 4, pitch=(1.0, 1.0, 4.0))
+    rows = [(3.0, -7.0, 1.0), (0.1, 5.0, 0.0), (6.2, -3.9, -2.0), (-1.0, 100.0, 0.5), (0.7, -3.9, -2.0),
+            (0.9, -100.0, 3.0), (np.nan, 0.0, 0.0), (0.1, 5.0, -0.0), (1.0, 0.0, -5.0), (0.2, np.inf, 0.0),
+            (0.2, -3.9, -3.0), (1e30, -7.0, 7.0), (-0.0, -8.0, 2.0), (np.pi / 4, 3.999, 1.0)]
+    pr = records(rows)
+    expected = ([2, 0, 0, 3, 0, 1, 4, 0, 1, 4, 0, 0, 0, 1], [0, 3, 1, 3, 1, 0, 0, 3, 2, 0, 1, 0, 0, 2],
+                [12, 11, 10, 2, 4, 1, 7, 5, 8, 13, 0, 3, 6, 9])
+    real_floor = np.floor
+    if mistake == "no_wrap":                      # angle bin not taken modulo the turn
+        monkeypatch.setattr(O.np, "mod", lambda a, n: a)
+    elif mistake == "truncate":                   # rounding toward zero instead of down
+        monkeypatch.setattr(O.np, "floor", np.trunc)
+    elif mistake == "no_half":                    # bins with edges, not centres, at multiples of dphi
+        calls = {"k": 0}
+
+        def floor_without_half(x):
+            calls["k"] += 1
+            return real_floor(x - 0.5) if calls["k"] == 1 else real_floor(x)
+        monkeypatch.setattr(O.np, "floor", floor_without_half)
+    elif mistake == "no_clamp":                   # heights outside the grid not clamped to its slabs
+        monkeypatch.setattr(O.np, "clip", lambda a, lo, hi: a)
+    elif mistake == "bins_by_degrees":            # angles taken as degrees
+        monkeypatch.setattr(O.np, "pi", 180.0)
+    with np.errstate(all="ignore"):
+        a, s_, _, _ = O.keys(grid, pr, 4, 4.0)
+        got = (a.tolist(), s_.tolist(), O.order(grid, pr, 4, 4.0).tolist())
+    assert got != expected
