@@ -277,8 +277,9 @@ typedef struct {
 } pct_sort_opts;
 
 /* Device workspace for pct_sort_scan on n records: 64 n bytes (keys,
- * positions and a packed copy of the records) plus about n / 16 bytes of
- * digit counts. */
+ * positions and a packed copy of the records) plus about n / 2 bytes of
+ * digit counts (256 per tile of 2048 records).  PCT_ERR_INVALID_ARG for
+ * n < 0, n >= 2^31 or bytes == NULL. */
 int pct_sort_scan_workspace_size(int64_t n, size_t *bytes);
 
 /* Writes the records (and b, if not NULL) to out in the order above, and, if
@@ -286,7 +287,9 @@ int pct_sort_scan_workspace_size(int64_t n, size_t *bytes);
  * int64[n]).  Needs p->n < 2^31, out->capacity >= p->n, b_out when b is given;
  * out, b_out and perm must not alias the input or each other.  ws: device,
  * 256-byte aligned, at least pct_sort_scan_workspace_size(p->n) bytes, used
- * as scratch.  Host-synchronous validation, asynchronous on `stream`. */
+ * as scratch.  Host-synchronous validation (PCT_ERR_INVALID_ARG for bad
+ * options or buffers, PCT_ERR_WORKSPACE for a missing, small or misaligned
+ * workspace; nothing is launched then), asynchronous on `stream`. */
 int pct_sort_scan(const pct_plan *plan, const pct_protons *p, const float *b, const pct_sort_opts *opts,
                   const pct_protons_buf *out, float *b_out, int64_t *perm, void *ws, size_t ws_bytes,
                   void *stream);
