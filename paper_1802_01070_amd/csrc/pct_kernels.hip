@@ -675,10 +675,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
                                                    unsigned long long *pk_cur, unsigned long long *pk_old, int *r_cur,
                                                    const int *r_prev, const int *r_old, int *r_reset,
                                                    const PathSrc src,  GridDev g, int64_t lo,
-                                                   int64_t hi, double lambda, unsigned *status, int nvox)
+                                                   int64_t hi, double lambda, unsigned *status, int nvox,
+                                                   int full)
 {
     if (int(blockIdx.x) < kCommitWG) {
-        commit_part(base, next, pk_prev, pk_old, r_prev, r_old, r_reset, nvox, int(blockIdx.x), kCommitWG);
+        commit_part(base, next, pk_prev, pk_old, r_prev, r_old, r_reset, nvox, int(blockIdx.x), kCommitWG, full);
         return;
     }
     using CT = float;
@@ -773,7 +774,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
             jmax = sc2.jmax;
         }
     }
-    publish_range(jmin, jmax, r_cur);
+    if (!full) publish_range(jmin, jmax, r_cur);   // full is uniform over the launch
 }
 
 // ---------------------------------------------------------------------------
@@ -1753,7 +1754,7 @@ static void launch_fused(int lanes, hipStream_t s, const ProtonsDev &p, const fl
                          float *next, const unsigned long long *pk_prev, unsigned long long *pk_cur,
                          unsigned long long *pk_old, int *r_cur, const int *r_prev, const int *r_old, int *r_reset,
                          const PathSrc &src, const GridDev &g, int64_t lo, int64_t hi, double lambda,
-                         unsigned *status, int nvox)
+                         unsigned *status, int nvox, int full)
 {
     const int64_t n = hi - lo;
     switch (lanes) {
@@ -1765,7 +1766,7 @@ static void launch_fused(int lanes, hipStream_t s, const ProtonsDev &p, const fl
             const size_t lds = size_t(64 / LPP) * 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<float>(); \
             hipLaunchKernelGGL((k_drop_fused<CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, base, next, \
                                pk_prev, pk_cur, pk_old, r_cur, r_prev, r_old, r_reset, src, g, lo, hi, lambda,  \
-                               status, nvox);                                                                    \
+                               status, nvox, full);                                                              \
         }                                                                                                        \
         break;                                                                                                   \
     }
@@ -2026,8 +2027,8 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                               [&](hipStream_t s, int64_t, int64_t lo, int64_t hi, const FusedStep &f) {
                                   launch_fused<CHORD, HULL>(lanes, s, p, b, f.base, f.next, f.pk_prev, f.pk_cur, f.pk_old,
                                                       f.r_cur, f.r_prev, f.r_old, f.r_reset, src, g, lo, hi,
-                                                      o.lambda, status, F.nv);
-                              });
+                                                      o.lambda, status, F.nv, 1);   // whole-volume commit
+                              }, 1);
                 return;
             }
         }
