@@ -333,7 +333,7 @@ int pct_rows_build(const pct_plan *plan, const pct_protons *p, int32_t chord_typ
 int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const float *b, void *x,
                           const pct_drop_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
-/* ---- multi-region reconstruction (Algorithm 1, Section II) ---------------
+/* ---- multi-region reconstruction (Algorithm 1, Section III) --------------
  * The volume is cut along z into overlapping slab regions; each proton goes to
  * every region holding both its entry slice (of v_in) and its exit slice (of
  * v_out); every region is solved on its own (any entry point above, on a

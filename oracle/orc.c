@@ -23,7 +23,9 @@
  *          1985) applied to every polyline segment; voxel of a sub-interval
  *          from its midpoint; half-open voxels; zero-length pieces dropped;
  *          consecutive pieces in the same voxel merged.
- *  row  -- a_ij = sum of the chords with voxel j (re-entries add).
+ *  row  -- a_ij = sum of the chords with voxel j (re-entries add).  A record
+ *          with a non-finite field measures nothing: its row is empty; a row
+ *          whose b_i (DROP) or r_i (back projection) is not finite is skipped.
  *  DROP -- block-iterative DROP of Censor, Elfving, Herman & Nikazad (SIAM J.
  *          Sci. Comput. 30:473, 2008) with unit row weights and the diagonal
  *          D = diag(1/s_j), s_j = number of rows of the block that touch j.
@@ -253,11 +255,16 @@ static void walk_segment(const orc_grid *g, const double P0[3], const double P1[
         if (d[a] == 0.0) continue;
         double lo = P0[a] < P1[a] ? P0[a] : P1[a];
         double hi = P0[a] < P1[a] ? P1[a] : P0[a];
-        /* candidate planes i = 0..n that may lie between the endpoints */
-        long i0 = (long)floor((lo - g->origin[a]) / g->pitch[a]) - 1;
-        long i1 = (long)ceil((hi - g->origin[a]) / g->pitch[a]) + 1;
-        if (i0 < 0) i0 = 0;
-        if (i1 > nn[a]) i1 = nn[a];
+        /* candidate planes i = 0..n that may lie between the endpoints; the
+         * bounds are clamped to [-1, n + 1] in floating point before the cast,
+         * so far-away (or non-finite) coordinates never overflow an integer */
+        double f0 = floor((lo - g->origin[a]) / g->pitch[a]) - 1.0;
+        double f1 = ceil((hi - g->origin[a]) / g->pitch[a]) + 1.0;
+        if (!(f0 >= 0.0)) f0 = 0.0;
+        if (f0 > nn[a] + 1.0) f0 = nn[a] + 1.0;
+        if (!(f1 <= nn[a])) f1 = nn[a];
+        if (f1 < -1.0) f1 = -1.0;
+        long i0 = (long)f0, i1 = (long)f1;
         for (long i = i0; i <= i1; i++) {
             double plane = g->origin[a] + i * g->pitch[a];
             double al = (plane - P0[a]) / d[a];
@@ -393,11 +400,21 @@ int orc_path(const orc_mlp *m, const double *tab, const orc_protons *p, int64_t 
     return n;
 }
 
+static int rec_finite(const orc_rec *r)
+{
+    return isfinite(r->t_in) && isfinite(r->v_in) && isfinite(r->th_in) && isfinite(r->ph_in) &&
+           isfinite(r->t_out) && isfinite(r->v_out) && isfinite(r->th_out) && isfinite(r->ph_out) &&
+           isfinite(r->phi);
+}
+
 /* Ordered emission list of proton i.  Returns the full list length; entries
- * beyond `cap` are not written. */
+ * beyond `cap` are not written.  A record with a non-finite field is no
+ * measurement: its row is empty (length 0). */
 int64_t orc_trace(const orc_grid *g, const orc_mlp *m, const double *tab, const orc_protons *p, int64_t i,
                   int64_t cap, int32_t *vox, double *chord)
 {
+    orc_rec rec = load_rec(p, i);
+    if (!rec_finite(&rec)) return 0;
     int K = orc_num_segments(m);
     int vcap = K + 3;
     double *P = (double *)malloc(sizeof(double) * 3 * vcap);
@@ -550,7 +567,8 @@ void orc_forward(const orc_grid *g, const orc_mlp *m, const orc_protons *p, int 
     free(tab);
 }
 
-/* g_j += sum_i a_ij r_i, accumulated in proton order (deterministic). */
+/* g_j += sum_i a_ij r_i, accumulated in proton order (deterministic); a row
+ * whose r_i is not finite contributes nothing. */
 void orc_backproject(const orc_grid *g, const orc_mlp *m, const orc_protons *p, int mode, const double *r, double *gout)
 {
     int K = orc_num_segments(m);
@@ -565,9 +583,11 @@ void orc_backproject(const orc_grid *g, const orc_mlp *m, const orc_protons *p, 
 #pragma omp parallel for schedule(dynamic, 64)
         for (int64_t i = lo; i < hi; i++)
             lens[i - lo] = build_row(g, m, tab, p, i, mode, &rows[i - lo], &caps[i - lo], NULL);
-        for (int64_t i = lo; i < hi; i++)
+        for (int64_t i = lo; i < hi; i++) {
+            if (!isfinite(r[i])) continue;
             for (int64_t k = 0; k < lens[i - lo]; k++)
                 gout[rows[i - lo][k].j] += rows[i - lo][k].a * r[i];
+        }
     }
     for (int64_t q = 0; q < chunk; q++) free(rows[q]);
     free(rows); free(caps); free(lens); free(tab);
@@ -580,6 +600,8 @@ void orc_backproject(const orc_grid *g, const orc_mlp *m, const orc_protons *p, 
  *     rho_i = lambda (b_i - a_i . xbar) / ||a_i||^2      (rows with ||a_i|| = 0 skipped)
  *     acc_j = sum_i rho_i a_ij,  s_j = #{i in block : a_ij != entry absent}
  *     x_j = xbar_j + acc_j / s_j                          for s_j > 0
+ * A row with a non-finite b_i (or a non-finite record, whose row is empty)
+ * is skipped like an empty row: it neither moves x nor counts in s_j.
  * blk_end < 0 means the last block.  Returns the number of blocks run per sweep. */
 int64_t orc_drop(const orc_grid *g, const orc_mlp *m, const orc_protons *p, const float *b, double *x,
                  int64_t B, double lambda, int n_iter, int64_t blk_begin, int64_t blk_end, int mode)
@@ -610,8 +632,10 @@ int64_t orc_drop(const orc_grid *g, const orc_mlp *m, const orc_protons *p, cons
                     dot += rows[q][k].a * x[rows[q][k].j];
                     n2 += rows[q][k].a * rows[q][k].a;
                 }
-                rho[q] = n2 > 0.0 ? lambda * ((double)b[i] - dot) / n2 : 0.0;
-                if (!(n2 > 0.0)) lens[q] = 0;
+                const double bi = (double)b[i];
+                const int use = n2 > 0.0 && isfinite(bi);
+                rho[q] = use ? lambda * (bi - dot) / n2 : 0.0;
+                if (!use) lens[q] = 0;
             }
             int64_t nt = 0;
             for (int64_t i = lo; i < hi; i++) {

@@ -1,11 +1,11 @@
 """FP64 oracle of the multi-region reconstruction (test infrastructure only).
 
-Algorithm 1 of the paper (Section II): the volume is cut along z into
+Algorithm 1 of the paper (Section III): the volume is cut along z into
 overlapping slab regions, each proton is given to every region that holds
 both the slice it enters the volume in and the slice it leaves it in, an
 independent iterative solve runs per region, and every overlapped slice is
 finally taken from the region whose own, non-overlapped slices are nearest
-(the selectSlice step).  Section II's example: 20 slices, two regions with
+(the selectSlice step).  Section III's example: 20 slices, two regions with
 slices 0-12 and 7-19, overlap 7-12, final image = slices 0-9 of the first
 region and 10-19 of the second.
 

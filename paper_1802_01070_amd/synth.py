@@ -303,7 +303,7 @@ WORKLOADS = {
                        block=3200, lam=0.1, n_iter=12, phantom="cyl200", order="angle_slab", seed=1007,
                        continuous_angles=True),
     # multi-region case: 20 slices like the reconstructions of the paper's
-    # Section II example (two regions, slices 0-12 and 7-19)
+    # Section III example (two regions, slices 0-12 and 7-19)
     "regions": ScanConfig("regions_cyl64x20", Grid(64, 64, 20), m=60_000, n_angles=90, r_hull=30.0, block=3200,
                           lam=0.1, n_iter=3, phantom="cyl64", value_type="f64", seed=1006),
     "tiny": ScanConfig("tiny_8x8x2", Grid(8, 8, 2), m=20_000, n_angles=90, r_hull=4.0, block=200,

@@ -1,4 +1,4 @@
-"""GPU parity of the multi-region reconstruction (Algorithm 1, Section II):
+"""GPU parity of the multi-region reconstruction (Algorithm 1, Section III):
 region selection bit-exact against the oracle's membership, slice copies, and
 the region-split DROP against the region-aware oracle."""
 import ctypes as C

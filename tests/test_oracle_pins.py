@@ -483,3 +483,160 @@ def test_quadratic_gradient_central_differences():
         lp, _ = oracle.tv_loss(sc.grid, sc.mlp, sc.protons, sc.b, x + e, beta, 1e-3)
         lm, _ = oracle.tv_loss(sc.grid, sc.mlp, sc.protons, sc.b, x - e, beta, 1e-3)
         assert g[v] == pytest.approx((lp - lm) / (2 * h), rel=1e-7, abs=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# non-finite inputs: a record with a non-finite field measures nothing (empty
+# row); a row whose b_i or r_i is not finite is skipped like an empty row
+# ---------------------------------------------------------------------------
+def _copy_protons(pr):
+    return {k: np.array(v, copy=True) for k, v in pr.items()}
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+@pytest.mark.parametrize("field", oracle.FIELDS)
+def test_nonfinite_record_has_empty_row(field, bad):
+    sc = synth.make_scan(synth.WORKLOADS[1], m=9)
+    pr = _copy_protons(sc.protons)
+    pr[field][4] = bad
+    _, ch0, nnz0 = oracle.trace(sc.grid, sc.mlp, sc.protons)
+    _, ch1, nnz1 = oracle.trace(sc.grid, sc.mlp, pr)
+    assert nnz0[4] > 0 and nnz1[4] == 0
+    keep = np.arange(9) != 4
+    np.testing.assert_array_equal(nnz0[keep], nnz1[keep])
+    np.testing.assert_array_equal(ch0[keep], ch1[keep])
+    y, n2, nd = oracle.forward(sc.grid, sc.mlp, pr, np.ones(sc.grid.nvox))
+    assert y[4] == 0.0 and n2[4] == 0.0 and nd[4] == 0
+    assert np.all(np.isfinite(y)) and np.all(np.isfinite(n2))
+
+
+def _miss_grid(pr, i, grid):
+    # a track passing 100 mm above the grid: its row is empty by geometry
+    z = grid.hi[2] + 100.0
+    for k, v in (("v_in", z), ("v_out", z), ("ph_in", 0.0), ("ph_out", 0.0)):
+        pr[k][i] = v
+
+
+def test_drop_skips_nonfinite_b_and_records_like_empty_rows():
+    sc = synth.make_scan(synth.WORKLOADS[1], m=1600)
+    grid, mlp = sc.grid, sc.mlp
+    bad = (3, 250, 251, 1111)
+    # reference: the same protons moved off the grid (empty rows)
+    pr_ref = _copy_protons(sc.protons)
+    for i in bad:
+        _miss_grid(pr_ref, i, grid)
+    _, _, nnz = oracle.trace(grid, mlp, pr_ref, bad[0], 1)
+    assert nnz[0] == 0
+    ref = oracle.drop(grid, mlp, pr_ref, sc.b, 1.0, block=400, lam=0.3, n_iter=2)
+    # non-finite b
+    b = sc.b.copy()
+    b[list(bad)] = [np.nan, np.inf, -np.inf, np.nan]
+    got_b = oracle.drop(grid, mlp, sc.protons, b, 1.0, block=400, lam=0.3, n_iter=2)
+    np.testing.assert_array_equal(got_b, ref)
+    # non-finite records (b finite)
+    pr = _copy_protons(sc.protons)
+    for i, f in zip(bad, ("gantry", "t_in", "th_out", "v_out")):
+        pr[f][i] = np.nan
+    got_r = oracle.drop(grid, mlp, pr, sc.b, 1.0, block=400, lam=0.3, n_iter=2)
+    np.testing.assert_array_equal(got_r, ref)
+    assert np.all(np.isfinite(ref))
+    # and the skipped rows did change the result of the plain scan
+    plain = oracle.drop(grid, mlp, sc.protons, sc.b, 1.0, block=400, lam=0.3, n_iter=2)
+    assert np.abs(plain - ref).max() > 0
+
+
+def test_backproject_skips_nonfinite_residuals():
+    sc = synth.make_scan(synth.WORKLOADS[1], m=300)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(sc.m)
+    r_bad = r.copy()
+    r_bad[[5, 77]] = [np.nan, np.inf]
+    r_zero = r.copy()
+    r_zero[[5, 77]] = 0.0
+    np.testing.assert_array_equal(oracle.backproject(sc.grid, sc.mlp, sc.protons, r_bad),
+                                  oracle.backproject(sc.grid, sc.mlp, sc.protons, r_zero))
+
+
+def test_far_away_finite_records_are_valid_rows():
+    # finite but huge coordinates: no integer overflow in the walk; every piece
+    # lies in the grid and the chords are finite and positive
+    sc = synth.make_scan(synth.WORKLOADS[1], m=6)
+    pr = _copy_protons(sc.protons)
+    pr["t_in"][0] = 1e30
+    pr["v_out"][1] = -3e38
+    pr["th_in"][2] = 1e20
+    pr["t_out"][3] = np.float32(-1e25)
+    vox, ch, nnz = oracle.trace(sc.grid, sc.mlp, pr)
+    for i in range(4):
+        n = int(nnz[i])
+        assert np.all((vox[i, :n] >= 0) & (vox[i, :n] < sc.grid.nvox))
+        assert np.all(np.isfinite(ch[i, :n])) and np.all(ch[i, :n] > 0)
+
+
+# ---------------------------------------------------------------------------
+# power iteration and gradient descent (differentiation form) against dense
+# linear algebra on the tiny scan
+# ---------------------------------------------------------------------------
+def _tv_numpy(grid, x, eps):
+    """Smoothed TV and its gradient from array differences (forward
+    differences, zero difference at the last index of each axis)."""
+    v = x.reshape(grid.nz, grid.ny, grid.nx)
+    dx = np.zeros_like(v)
+    dy = np.zeros_like(v)
+    dz = np.zeros_like(v)
+    dx[:, :, :-1] = np.diff(v, axis=2)
+    dy[:, :-1, :] = np.diff(v, axis=1)
+    dz[:-1, :, :] = np.diff(v, axis=0)
+    s = np.sqrt(dx * dx + dy * dy + dz * dz + eps * eps)
+    g = -(dx + dy + dz) / s
+    g[:, :, 1:] += (dx / s)[:, :, :-1]
+    g[:, 1:, :] += (dy / s)[:, :-1, :]
+    g[1:, :, :] += (dz / s)[:-1, :, :]
+    return float(s.sum()), g.ravel()
+
+
+def test_power_iteration_matches_dense_eigenvalue():
+    sc = synth.make_scan(synth.WORKLOADS["tiny"], m=1500)
+    A = _dense_rows(sc, 0, sc.m)
+    w, V = np.linalg.eigh(A.T @ A)
+    lam_max = float(w[-1])
+    # from the top eigenvector one step gives lambda_max exactly
+    assert oracle.power_iteration(sc.grid, sc.mlp, sc.protons, V[:, -1], 1) == pytest.approx(lam_max, rel=1e-12)
+    v0 = synth.power_start(sc.grid.nvox, 4)
+    # ||A^T A v|| <= lambda_max ||v|| for every step count, and it converges
+    lam20 = oracle.power_iteration(sc.grid, sc.mlp, sc.protons, v0, 20)
+    assert lam20 <= lam_max * (1 + 1e-12)
+    gap = float(w[-2] / w[-1])
+    n = int(np.ceil(np.log(1e-13) / np.log(gap) / 2)) + 5
+    lam_n = oracle.power_iteration(sc.grid, sc.mlp, sc.protons, v0, n)
+    assert lam_n == pytest.approx(lam_max, rel=1e-10)
+    assert lam20 >= lam_max * (1 - 2 * gap ** 38)   # error of the 20-step estimate (Rayleigh-type bound)
+
+
+def test_tv_numpy_reference_matches_oracle_tv():
+    grid = Grid(6, 5, 4)
+    x = np.random.default_rng(6).random(grid.nvox)
+    val, g = oracle.tv(grid, x, 1e-2)
+    vn, gn = _tv_numpy(grid, x, 1e-2)
+    assert val == pytest.approx(vn, rel=1e-13)
+    np.testing.assert_allclose(g, gn, rtol=1e-12, atol=1e-14)
+
+
+def test_gradient_descent_matches_dense_iteration():
+    sc = synth.make_scan(synth.WORKLOADS["tiny"], m=1200)
+    A = _dense_rows(sc, 0, sc.m)
+    b = sc.b.astype(np.float64)
+    beta, eps, n_steps = 1e-2, 1e-3, 6
+    x0 = synth.power_start(sc.grid.nvox, 9)
+    eta = 1.0 / (float(np.linalg.eigvalsh(A.T @ A)[-1]) + 12 * beta / eps)
+    x = x0.copy()
+    losses = []
+    for _ in range(n_steps):
+        r = A @ x - b
+        tv_val, tv_g = _tv_numpy(sc.grid, x, eps)
+        losses.append(0.5 * float(r @ r) + beta * tv_val)
+        x = x - eta * (A.T @ r + beta * tv_g)
+    got_x, got_l = oracle.gradient_descent(sc.grid, sc.mlp, sc.protons, sc.b, x0, beta, eps, eta, n_steps)
+    np.testing.assert_allclose(got_l, losses, rtol=1e-11)
+    np.testing.assert_allclose(got_x, x, rtol=1e-10, atol=1e-12)
+    assert losses[-1] < losses[0]

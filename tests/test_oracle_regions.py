@@ -1,4 +1,4 @@
-"""Pins of the multi-region oracle (Algorithm 1, Section II) against what the
+"""Pins of the multi-region oracle (Algorithm 1, Section III) against what the
 paper and the mathematics fix: the paper's own 20-slice example, the cases
 where the split must reduce to the single-volume solve, the coverage
 guarantee of the overlap, and the restriction of a row to a region's slices."""
