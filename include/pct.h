@@ -183,25 +183,44 @@ typedef struct {
 #define PCT_DROP_NO_GRAPH 0x2u     /* launch per block on the stream, no HIP graph   */
 #define PCT_DROP_PROFILE 0x4u      /* bracket a sample of the per-block kernels with
                                       HIP events on `stream` (see pct_profile_read) */
-/* FP32 value type with lanes > 1: by default the commit of block t-1 runs
- * inside the launch of block t (block t reads x + D * block sum of t-1, the
- * value the commit writes, so the result is bitwise that of the separate
- * schedule).  This flag asks for the separate schedule: one block kernel and
- * one commit kernel per block. */
+/* Block schedules of the FP32 value type with lanes > 1 (DROP's block step,
+ * Section IV-B: all rows of block t against the same iterate, then the
+ * D-weighted back-projection committed before block t+1).
+ *
+ * Default, when the workspace holds the slab bins of B rows (pct_workspace_size
+ * with n >= B) and max(nx, ny) <= 8192: the binned schedule.  Per block, one
+ * launch walks the rows and stores each lane's packed contributions (row count
+ * bit + fixed-point rho_i a_ij) into per-(slab, row) bins of the block's
+ * dominant in-plane axis; a second launch sums each slab's bins in LDS, one
+ * workgroup per slab, and commits x_j += acc_j / s_j over exactly the touched
+ * voxels.  The per-voxel integer sums equal those of the atomic schedules.
+ * By default the commit carries the FP32 iterate's rounding error in a second
+ * FP32 word per voxel (workspace, zeroed at the start of each call), so x is
+ * rounded once per call rather than once per commit; the gathers read the
+ * FP32 x.  Without a workspace large enough, the fused schedules below run. */
+#define PCT_DROP_NO_COMPENSATION 0x40u /* binned schedule: round x at every commit
+                                          (bitwise the atomic schedules' result) */
+/* The atomic schedules: every piece is one 64-bit atomic into a packed
+ * block accumulator.  Fused: the commit of block t-1 runs inside the launch
+ * of block t (block t reads x + D * block sum of t-1, the value the commit
+ * writes, so the result is bitwise that of the separate schedule). */
+#define PCT_DROP_FUSED_COMMIT 0x20u
+/* The separate schedule: one block kernel and one commit kernel per block
+ * (also the FP64 value type's schedule). */
 #define PCT_DROP_SEPARATE_COMMIT 0x8u
-/* FP32 value type, 64 lanes per proton, blocks of at most 4096 protons,
- * workspace sized for the block (see pct_workspace_size): by default the rows
- * of block t+1 are traced in the launch that runs the DROP step of block t
- * (the rows do not depend on x), so each block step no longer waits for its
- * own walk; results are bitwise those of the other schedules.  Larger blocks
- * take the plain fused schedule (faster there).  This flag asks for the plain
+/* Fused schedule, 64 lanes per proton, blocks of at most 4096 protons,
+ * workspace sized for the block: by default the rows of block t+1 are traced
+ * in the launch that runs the DROP step of block t (the rows do not depend on
+ * x), so each block step no longer waits for its own walk; results are
+ * bitwise those of the other atomic schedules.  This flag asks for the plain
  * fused schedule. */
 #define PCT_DROP_NO_TRACE_AHEAD 0x10u
 
-/* Workspace bytes for this plan and x of type dtype.  n > 0 adds two row
- * slots for DROP blocks of up to n protons, which the traced-ahead schedule
- * needs (2 * n * 6.4 KB); with n = 0 pct_drop_iterate uses the other
- * schedules. */
+/* Workspace bytes for this plan and x of type dtype.  n > 0 adds, for DROP
+ * blocks of up to n protons, two row slots (the traced-ahead schedule,
+ * 2 * n * 6.4 KB) and the slab bins of the binned schedule
+ * (max(nx, ny) * n * 64 B + 2 * max(nx, ny) * n B); with n = 0 pct_drop_iterate
+ * uses the atomic schedules. */
 int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes);
 
 /* Writes the coefficient table into the workspace and clears its counters and

@@ -20,6 +20,8 @@ PCT_DROP_NO_GRAPH = 0x2
 PCT_DROP_PROFILE = 0x4
 PCT_DROP_SEPARATE_COMMIT = 0x8
 PCT_DROP_NO_TRACE_AHEAD = 0x10
+PCT_DROP_FUSED_COMMIT = 0x20
+PCT_DROP_NO_COMPENSATION = 0x40
 DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range", 0x10: "bad_row"}
 FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out", "gantry")
 

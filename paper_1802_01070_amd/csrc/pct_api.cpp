@@ -43,6 +43,8 @@ Layout layout_for(int64_t nvox, int K, int dtype)
     off = align256(off + size_t(nvox) * sizeof(double));
     L.partial = off;
     off = align256(off + size_t(kMaxPartials) * sizeof(double));
+    L.lo = off;
+    off = align256(off + size_t(nvox) * sizeof(float));
     L.total = off;
     return L;
 }
@@ -348,7 +350,8 @@ int pct_plan_table(const pct_plan *plan, double *tab, int64_t tab_len)
 int pct_workspace_size(const pct_plan *plan, int64_t n, int32_t dtype, size_t *bytes)
 {
     if (!plan || !bytes || n < 0 || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
-    *bytes = layout_for(plan->nvox, plan->K, dtype).total + (n > 0 ? 2 * slot_bytes(n) : 0);
+    const int nslab = std::max(plan->grid.nx, plan->grid.ny);
+    *bytes = layout_for(plan->nvox, plan->K, dtype).total + (n > 0 ? 2 * slot_bytes(n) + bin_bytes(n, nslab) : 0);
     return PCT_OK;
 }
 
@@ -432,7 +435,7 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
     if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
     if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT |
-                     PCT_DROP_NO_TRACE_AHEAD))
+                     PCT_DROP_NO_TRACE_AHEAD | PCT_DROP_FUSED_COMMIT | PCT_DROP_NO_COMPENSATION))
         return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
     if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 20)) return PCT_ERR_INVALID_ARG;

@@ -57,7 +57,8 @@ struct Layout {
     size_t cnt;      // nvox int32
     size_t x1;       // second copy of the iterate, nvox doubles
     size_t partial;  // kMaxPartials doubles
-    size_t total;    // end of the fixed part; the traced-ahead row slots follow
+    size_t lo;       // compensation word of the FP32 iterate, nvox floats
+    size_t total;    // end of the fixed part; the traced-ahead row slots and the bins follow
 
 };
 constexpr int kMaxPartials = 4096;
@@ -65,11 +66,27 @@ constexpr int kMaxPartials = 4096;
 // 64 lane counts and ||a_i||^2 (two slots of B records follow Layout::total).
 constexpr size_t kSlotRecordBytes = size_t(12) * 64 * 8 + 64 * 4 + 8;
 inline size_t slot_bytes(int64_t records) { return (size_t(records) * kSlotRecordBytes + 255) & ~size_t(255); }
+// Slab bins of the binned schedule (after the two row slots): per slab of the
+// block's dominant axis and row of the block, kBinCap entries (a packed
+// 64-bit word each, the voxel index of entries 1.. in a second array) and, per
+// block parity, the voxel index of entry 0 with the entry count in its top
+// bits: 52 bytes per (slab, row).  Rows are rounded up to a multiple of 16;
+// blocks of the binned schedule hold at most kBinMaxRows rows.
+constexpr int kBinCap = 4;
+constexpr int kBinMaxRows = 8192;
+constexpr int kWinWords = 16384;  // LDS window of a slab commit: 128 KB of packed words
+inline int64_t bin_rows(int64_t records) { return (records + 15) & ~int64_t(15); }
+inline size_t bin_bytes(int64_t records, int nslab)
+{
+    const size_t nrow = size_t(nslab) * size_t(bin_rows(records));
+    return (nrow * (kBinCap * 8 + (kBinCap - 1) * 4 + 2 * 4) + 255) & ~size_t(255);
+}
 
 // header words (int32 index): status word, then the [jmin, jmax] voxel range
-// touched by a block, double-buffered by block parity (FP64 path), and four
-// rotating range slots of the fused FP32 path
-enum : int { kHdrStatus = 0, kHdrRange0 = 2, kHdrRange1 = 4, kHdrSlots = 8 };
+// touched by a block, double-buffered by block parity (FP64 path), four
+// rotating range slots of the fused FP32 path, and the two overflow flags of
+// the binned schedule (by block parity)
+enum : int { kHdrStatus = 0, kHdrRange0 = 2, kHdrRange1 = 4, kHdrSlots = 8, kHdrOvf = 16 };
 
 Layout layout_for(int64_t nvox, int K, int dtype);
 

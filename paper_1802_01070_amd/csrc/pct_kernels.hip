@@ -993,6 +993,374 @@ __global__ void __launch_bounds__(256) k_sweep_end(float *x, const float *src, u
     }
 }
 
+// ---------------------------------------------------------------------------
+// Binned FP32 schedule: the block's D-weighted back-projection is staged per
+// slab of the block's dominant axis and summed in LDS, one workgroup per slab.
+//
+// Launch 1 (k_drop_bin) runs the proton groups exactly as k_drop_fused does
+// (walk, a_i.x against the committed iterate, ||a_i||^2, rho_i), but each lane
+// stores its packed contributions (the same 64-bit word: row count bit plus
+// rho_i a_ij in fixed point) into the bin of the piece's slab,
+// bins[s][p][0..kBinCap), with the number of entries in cnt[s][p].  Lanes own
+// disjoint slab ranges, so every (slab, proton) bin has a single writer: plain
+// stores, no atomics.  Pieces without a bin (a proton whose dominant axis is
+// not the block's, a path that is not monotone along it, more than kBinCap
+// pieces of one row in one slab) go to a packed overflow accumulator with a
+// global atomic, and raise the block's overflow flag.
+//
+// Launch 2 (k_slab_commit) gives each slab (and z chunk) of the block's axis
+// to one workgroup: it adds the slab's bin entries into a dense LDS window of
+// the slab (64-bit integer adds), adds the overflow words of the window when
+// the flag is up, and commits x_j = x_j + sum_j / s_j for every voxel of the
+// window the block touched.  The integer sums per voxel are the ones the
+// atomic schedules form, so without compensation the result is bitwise
+// theirs; slabs are disjoint, so the commit is a plain read-modify-write of x
+// over exactly the touched voxels.
+//
+// Compensation (default): the commit keeps the rounding error of the FP32
+// iterate in a second FP32 word per voxel (lo, zero at the start of a call),
+// forms base = x_j + lo_j + sum_j / s_j in FP64 and stores x_j = fl32(base),
+// lo_j = fl32(base - x_j).  The gathers read x_j (the FP32 high part); x_j is
+// the iterate rounded once, whatever the number of commits.
+// ---------------------------------------------------------------------------
+constexpr int kSlabWG = 1024;  // threads of a slab-commit workgroup
+
+struct BinsDev {
+    unsigned long long *w;  // [slab][kBinCap][cap]: packed words, entry-major (a slab's first
+                            // entries are contiguous)
+    unsigned *j1;           // [slab][kBinCap - 1][cap]: voxel index of entries 1.. of each bin
+    unsigned *j0;           // [parity][slab][cap]: voxel index of entry 0 | (entries - 1) << 30,
+                            // kEmptyBin for a bin without entries
+    int cap;                // rows per block the bins hold (a multiple of 16)
+    int nslab;              // max(nx, ny)
+};
+constexpr unsigned kEmptyBin = 0xFFFFFFFFu;
+
+// Dominant in-plane axis of the block: the walk's test on its first record.
+__device__ __forceinline__ int block_axis(const ProtonsDev &p, int64_t lo)
+{
+    double sn, cs;
+    sincos(double(p.gantry[lo]), &sn, &cs);
+    return fabs(cs) >= fabs(sn) ? 0 : 1;
+}
+
+// One lane's pieces, in walk order (slab by slab in the direction of travel),
+// into the bins of row p of the block.  A slab's first entry is held until the
+// lane leaves the slab, then stored with the bin's entry count in the top bits
+// of its voxel word; further entries are stored as they come.
+struct BinWriter {
+    BinsDev bins;
+    int par, axis, nx, ny;
+    int p;
+    bool direct;  // the row has no bins: every piece to the overflow accumulator
+    unsigned long long *ovf;
+    int *ovf_flag;
+    int cur, k;
+    unsigned long long w0;
+    unsigned j0;
+
+    __device__ __forceinline__ void overflow(unsigned j, unsigned long long w)
+    {
+        atomicAdd(ovf + j, w);
+        *ovf_flag = 1;
+    }
+    __device__ __forceinline__ void flush()
+    {
+        if (cur >= 0) {
+            const size_t q = size_t(cur) * bins.cap + p;
+            bins.w[size_t(cur) * kBinCap * bins.cap + p] = w0;
+            bins.j0[size_t(par) * bins.nslab * bins.cap + q] = j0 | (unsigned(min(k, kBinCap) - 1) << 30);
+        }
+        cur = -1;
+    }
+    __device__ __forceinline__ void put(int jj, unsigned long long w)
+    {
+        const unsigned j = unsigned(jj);
+        if (direct) {
+            overflow(j, w);
+            return;
+        }
+        const int s = axis == 0 ? int(j % unsigned(nx)) : int((j / unsigned(nx)) % unsigned(ny));
+        if (s != cur) {
+            flush();
+            cur = s;
+            k = 0;
+        }
+        if (k == 0) {
+            w0 = w;
+            j0 = j;
+        } else if (k < kBinCap) {
+            bins.w[(size_t(s) * kBinCap + k) * bins.cap + p] = w;
+            bins.j1[(size_t(s) * (kBinCap - 1) + (k - 1)) * bins.cap + p] = j;
+        } else {
+            overflow(j, w);
+        }
+        ++k;
+    }
+};
+
+// Walk sink of a lane that re-walks its slabs (stash overflow): packed
+// contributions straight into the bins.
+struct BinScatterSink {
+    BinWriter *bw;
+    unsigned *status;
+    Reentry re;
+    double rho;
+    __device__ __forceinline__ void segment(double dx, double dy) { re.segment(dx, dy); }
+    __device__ __forceinline__ void final(int j, int ix, int iy, int iz, double c)
+    {
+        bool first;
+        re.visit(j, ix, iy, iz, c, first);
+        bw->put(j, pack_contribution(rho * c, first, status));
+    }
+};
+
+template <int CHORD, int LPP, bool HULL>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ x, BinsDev bins, int par,
+           unsigned long long *ovf, int *ovf_flag, const PathSrc src, GridDev g, int64_t lo, int64_t hi,
+           double lambda, unsigned *status)
+{
+    using CT = float;
+    extern __shared__ double lds[];
+    constexpr int GPW = 64 / LPP;
+    const int lane = threadIdx.x;
+    const int grp = lane / LPP;
+    const int l = lane % LPP;
+    // XCD-aware placement as in k_drop_fused: contiguous runs of the block per XCD
+    const int wq = int(blockIdx.x);
+    const int64_t n_wg = (hi - lo + GPW - 1) / GPW;
+    const int64_t per_xcd = (n_wg + 7) / 8;
+    const int64_t wg = int64_t(wq % 8) * per_xcd + wq / 8;
+    const int64_t i = lo + wg * GPW + grp;
+    bool active = wg < n_wg && i < hi;
+    Rec r{};
+    double bi = 0.0;
+    if (active) {
+        r = load_rec(p, i);
+        bi = double(b[i]);
+        if (!rec_finite(r) || !isfinite(bi)) {
+            if (l == 0) raise_status(status, PCT_DEV_NONFINITE);
+            active = false;
+        }
+    }
+    if (!active) r.cs = 1.0, r.sn = 0.0;
+    double *P = lds + grp * 3 * src.nvmax;
+    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * src.nvmax);
+    int *sj = reinterpret_cast<int *>(stash);
+    CT *sc = reinterpret_cast<CT *>(stash + size_t(64) * kStash * sizeof(int));
+    const GroupPath gp = stage_path<LPP, HULL>(r, src, g, P, l, active);
+
+    StashSink<CT, kStash> st{sj, sc, lane, {}, 0.0, 0};
+    st.re.init(r);
+    {
+        Merge<StashSink<CT, kStash>, CHORD> m(st, g);
+        walk_lane<LPP>(gp, l, g, P, m);
+        m.finish();
+    }
+    if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
+    const bool spill = st.count > kStash;
+    const int ns = min(st.count, kStash);
+    const PlainX<float> xa{x};
+    double dot = 0.0;
+    if (!spill) {
+#pragma unroll 4
+        for (int q = 0; q < ns; ++q) {
+            const int j = sj[q * 64 + lane] & 0x7FFFFFFF;
+            dot += double(sc[q * 64 + lane]) * xa(j);
+        }
+    } else {
+        DotSink<float> ds;
+        ds.x = xa;
+        ds.dot = 0.0;
+        ds.n2 = 0.0;
+        ds.re.init(r);
+        Merge<DotSink<float>, CHORD> m(ds, g);
+        walk_lane<LPP>(gp, l, g, P, m);
+        m.finish();
+        dot = ds.dot;
+    }
+    dot = group_sum<LPP>(dot);
+    const double n2 = group_sum<LPP>(st.n2);
+    if (n2 > 0.0) {
+        const double rho = lambda * (bi - dot) / n2;
+        const int axis = block_axis(p, lo);
+        BinWriter bw{bins, par, axis, g.n[0], g.n[1], int(i - lo), gp.full || gp.dom != axis, ovf, ovf_flag, -1, 0, 0ull, 0u};
+        if (!spill) {
+            for (int q = 0; q < ns; ++q) {
+                const int e = sj[q * 64 + lane];
+                bw.put(e & 0x7FFFFFFF, pack_contribution(rho * double(sc[q * 64 + lane]), e < 0, status));
+            }
+        } else {
+            BinScatterSink ss{&bw, status, {}, rho};
+            ss.re.init(r);
+            Merge<BinScatterSink, CHORD> m(ss, g);
+            walk_lane<LPP>(gp, l, g, P, m);
+            m.finish();
+        }
+        bw.flush();
+    }
+}
+
+// Start of a binned sweep: every bin of both parities empty and both overflow
+// flags zero.
+__global__ void __launch_bounds__(256) k_bins_begin(unsigned *j0, size_t n, int *ovf_flag)
+{
+    const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < 2) ovf_flag[t] = 0;
+    uint4 *c4 = reinterpret_cast<uint4 *>(j0);
+    for (size_t q = t; q < n / 4; q += size_t(gridDim.x) * blockDim.x)
+        c4[q] = make_uint4(kEmptyBin, kEmptyBin, kEmptyBin, kEmptyBin);
+}
+
+__global__ void __launch_bounds__(256) k_zero_f32(float *v, int64_t n)
+{
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += int64_t(gridDim.x) * blockDim.x)
+        v[q] = 0.f;
+}
+
+// Commit of block [lo, lo + nb) of the binned schedule: workgroup
+// (slab s, z chunk zi) sums the slab's bins into its LDS window and commits
+// the touched voxels.  Workgroups of chunk 0 also empty the other parity's
+// bins of their slab (read by the previous block's commit) and clear the other
+// parity's overflow flag.  Thread t takes rows t, t + kSlabWG, ... of the
+// block: the first entries of its rows are read coalesced, all at once, then
+// the second entries of the rows that have them, then the rare rest; in the
+// commit it takes a fixed set of window cells whose x loads are issued before
+// any store.
+constexpr int kRowsPerThread = 8;   // rows of a block per slab-commit thread
+constexpr int kCommitCells = 16;    // window cells per thread and pass of the commit
+
+__device__ __forceinline__ void window_add(unsigned long long *win, unsigned j, unsigned long long w, int axis,
+                                           int nlat, int z0, int z1, unsigned nx, unsigned nxy)
+{
+    const unsigned iz = j / nxy;
+    const unsigned rr = j - iz * nxy;
+    const unsigned iy = rr / nx;
+    const unsigned ix = rr - iy * nx;
+    const int zz = int(iz) - z0;
+    if (zz >= 0 && int(iz) < z1) atomicAdd(&win[int(axis == 0 ? iy : ix) + nlat * zz], w);
+}
+
+__global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t lo, int nb, BinsDev bins, int par,
+                                                         unsigned long long *ovf, int *ovf_flag,
+                                                         float *__restrict__ x, float *__restrict__ xlo, GridDev g,
+                                                         int zc, int nzc, int comp)
+{
+    extern __shared__ unsigned long long win[];
+    const int tid = int(threadIdx.x);
+    const int s = int(blockIdx.x) / nzc, zi = int(blockIdx.x) % nzc;
+    if (zi == 0) {
+        uint4 *c2 = reinterpret_cast<uint4 *>(bins.j0 + (size_t(1 - par) * bins.nslab + s) * bins.cap);
+        for (int q = tid; q < bins.cap / 4; q += kSlabWG) c2[q] = make_uint4(kEmptyBin, kEmptyBin, kEmptyBin, kEmptyBin);
+        if (s == 0 && tid == 0) ovf_flag[1 - par] = 0;
+    }
+    const int axis = block_axis(p, lo);
+    if (s >= g.n[axis]) return;
+    const int nlat = g.n[1 - axis];
+    const int z0 = zi * zc, z1 = min(g.n[2], z0 + zc);
+    if (z0 >= z1) return;
+    const int nw = nlat * (z1 - z0);
+    for (int q = tid; q < nw; q += kSlabWG) win[q] = 0ull;
+    __syncthreads();
+    const unsigned *j0 = bins.j0 + (size_t(par) * bins.nslab + s) * bins.cap;
+    const unsigned long long *w = bins.w + size_t(s) * kBinCap * bins.cap;
+    const unsigned *j1 = bins.j1 + size_t(s) * (kBinCap - 1) * bins.cap;
+    const int cap = bins.cap;
+    const unsigned nx = unsigned(g.n[0]), nxy = unsigned(g.n[0]) * unsigned(g.n[1]);
+    unsigned jr[kRowsPerThread];
+    unsigned long long wr[kRowsPerThread];
+#pragma unroll
+    for (int m = 0; m < kRowsPerThread; ++m) {
+        const int r = tid + m * kSlabWG;
+        jr[m] = kEmptyBin;
+        wr[m] = 0ull;
+        if (r < nb) {
+            jr[m] = j0[r];
+            wr[m] = w[r];
+        }
+    }
+    // second entries of the rows with two or more (one batch of loads)
+    unsigned jb[kRowsPerThread];
+    unsigned long long wb[kRowsPerThread];
+#pragma unroll
+    for (int m = 0; m < kRowsPerThread; ++m) {
+        const int r = tid + m * kSlabWG;
+        jb[m] = kEmptyBin;
+        wb[m] = 0ull;
+        if (jr[m] != kEmptyBin && (jr[m] >> 30) >= 1u) {
+            jb[m] = j1[r];
+            wb[m] = w[cap + r];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kRowsPerThread; ++m) {
+        if (jr[m] == kEmptyBin) continue;
+        const int c = int(jr[m] >> 30) + 1;
+        window_add(win, jr[m] & 0x3FFFFFFFu, wr[m], axis, nlat, z0, z1, nx, nxy);
+        if (c >= 2) window_add(win, jb[m], wb[m], axis, nlat, z0, z1, nx, nxy);
+        for (int k = 2; k < c; ++k) {
+            const int r = tid + m * kSlabWG;
+            window_add(win, j1[size_t(k - 1) * cap + r], w[size_t(k) * cap + r], axis, nlat, z0, z1, nx, nxy);
+        }
+    }
+    const bool of = ovf_flag[par] != 0;
+    __syncthreads();
+    for (int q0 = 0; q0 < nw; q0 += kCommitCells * kSlabWG) {
+        int jv[kCommitCells];
+        unsigned long long wv[kCommitCells];
+        float xv[kCommitCells], lv[kCommitCells];
+#pragma unroll
+        for (int u = 0; u < kCommitCells; ++u) {
+            const int q = q0 + tid + u * kSlabWG;
+            jv[u] = -1;
+            wv[u] = 0ull;
+            if (q < nw) {
+                const int a = q % nlat, zz = z0 + q / nlat;
+                const int ix = axis == 0 ? s : a, iy = axis == 0 ? a : s;
+                jv[u] = ix + g.n[0] * (iy + g.n[1] * zz);
+                wv[u] = win[q];
+            }
+        }
+        if (of) {
+#pragma unroll
+            for (int u = 0; u < kCommitCells; ++u) {
+                if (jv[u] >= 0) {
+                    const unsigned long long o = ovf[jv[u]];
+                    if (o != 0ull) {
+                        wv[u] += o;
+                        ovf[jv[u]] = 0ull;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCommitCells; ++u) {
+            xv[u] = 0.f;
+            lv[u] = 0.f;
+            if (wv[u] != 0ull) {
+                xv[u] = x[jv[u]];
+                if (comp) lv[u] = xlo[jv[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCommitCells; ++u) {
+            if (wv[u] == 0ull) continue;
+            if (comp) {
+                int c;
+                double sum;
+                unpack_accumulator(wv[u], c, sum);
+                const double v = double(xv[u]) + double(lv[u]) + sum / double(c);
+                const float h = float(v);
+                x[jv[u]] = h;
+                xlo[jv[u]] = float(v - double(h));
+            } else {
+                x[jv[u]] = committed_value(xv[u], wv[u]);
+            }
+        }
+    }
+}
+
 // Commit of one block: a dense, coalesced scan of the block's touched index
 // range; voxels with a non-zero row count get x_j += acc_j / s_j and are reset.
 // Also re-arms the range words of the next block.
@@ -1779,6 +2147,50 @@ static void launch_fused(int lanes, hipStream_t s, const ProtonsDev &p, const fl
     }
 }
 
+static_assert(kRowsPerThread * kSlabWG >= kBinMaxRows, "slab commit covers the largest binned block");
+
+// Packed words of a slab-commit window: 128 KB of LDS once the kernel is
+// allowed that much dynamic LDS, else 64 KB.
+static int slab_window_words()
+{
+    static const int words = [] {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_slab_commit),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 int(kWinWords * sizeof(unsigned long long)));
+        (void)hipGetLastError();
+        return e == hipSuccess ? kWinWords : kWinWords / 2;
+    }();
+    return words;
+}
+
+// Launch of block [lo, hi) of the binned schedule (see k_drop_bin).
+template <int CHORD, bool HULL>
+static void launch_bin(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, const float *x,
+                       const BinsDev &bins, int par, unsigned long long *ovf, int *ovf_flag, const PathSrc &src,
+                       const GridDev &g, int64_t lo, int64_t hi, double lambda, unsigned *status)
+{
+    const int64_t n = hi - lo;
+    switch (lanes) {
+#define PCT_LAUNCH_BIN(LPP)                                                                                      \
+    case LPP: {                                                                                                  \
+        if constexpr (!HULL || LPP == 64) {                                                                      \
+            const int64_t n_wg = (n + (64 / LPP) - 1) / (64 / LPP);                                          \
+            const unsigned grid = unsigned(8 * ((n_wg + 7) / 8));                                            \
+            const size_t lds = size_t(64 / LPP) * 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<float>(); \
+            hipLaunchKernelGGL((k_drop_bin<CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, bins, par, \
+                               ovf, ovf_flag, src, g, lo, hi, lambda, status);                                  \
+        }                                                                                                        \
+        break;                                                                                                   \
+    }
+        PCT_LAUNCH_BIN(8)
+        PCT_LAUNCH_BIN(16)
+        PCT_LAUNCH_BIN(32)
+        PCT_LAUNCH_BIN(64)
+#undef PCT_LAUNCH_BIN
+    default: break;
+    }
+}
+
 // Lanes per proton: enough lanes that each walks a few slabs of the dominant
 // axis, within the LDS budget of the staged vertex coordinates.
 constexpr int64_t kPipeMaxBlock = 4096;
@@ -1972,7 +2384,15 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
             }
         }
     };
-    const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT);
+    // binned schedule (FP32 default): the workspace holds the slab bins of a
+    // block and a slab's window fits the LDS budget
+    const int nslab = std::max(pl.grid.nx, pl.grid.ny);
+    const int win_words = sizeof(T) == 4 ? slab_window_words() : 0;
+    const bool binned = sizeof(T) == 4 && lanes > 1 && !(o.flags & (PCT_DROP_SEPARATE_COMMIT | PCT_DROP_FUSED_COMMIT)) &&
+                        nslab <= win_words && o.block <= kBinMaxRows && pl.nvox < (int64_t(1) << 30) &&
+                        ws_bytes >= L.total + 2 * slot_bytes(o.block) + bin_bytes(o.block, nslab);
+    const bool comp = binned && !(o.flags & PCT_DROP_NO_COMPENSATION);
+    const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT) && !binned;
     // tracing ahead doubles the workgroups of a launch; with blocks above
     // kPipeMaxBlock protons the plain fused schedule is the faster one
     // (measured: 3200-proton blocks 165 vs 169 ms per sweep traced ahead, 6400-proton
@@ -1981,6 +2401,49 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                       ws_bytes >= L.total + 2 * slot_bytes(o.block);
     auto sweep = [&](hipStream_t s, bool record_events) {
         if constexpr (sizeof(T) == 4) {
+            if (binned) {
+                BinsDev bins;
+                const int64_t cap = bin_rows(o.block);
+                char *bbase = wsb(ws) + L.total + 2 * slot_bytes(o.block);
+                const size_t nrow = size_t(nslab) * size_t(cap);
+                bins.w = reinterpret_cast<unsigned long long *>(bbase);
+                bins.j1 = reinterpret_cast<unsigned *>(bbase + nrow * kBinCap * 8);
+                bins.j0 = reinterpret_cast<unsigned *>(bbase + nrow * (kBinCap * 8 + (kBinCap - 1) * 4));
+                bins.cap = int(cap);
+                bins.nslab = nslab;
+                const size_t ncnt = 2 * nrow;
+                int *ovf_flag = hdr + kHdrOvf;
+                unsigned long long *ovf = static_cast<unsigned long long *>(acc);
+                const int zc = std::min(pl.grid.nz, win_words / nslab);
+                const int nzc = (pl.grid.nz + zc - 1) / zc;
+                const size_t win_lds = size_t(nslab) * size_t(zc) * sizeof(unsigned long long);
+                float *xlo = reinterpret_cast<float *>(wsb(ws) + L.lo);
+                hipLaunchKernelGGL(k_bins_begin, dim3(unsigned(std::min<size_t>(1024, (ncnt / 4 + 255) / 256 + 1))),
+                                   dim3(256), 0, s, bins.j0, ncnt, ovf_flag);
+                int64_t seq = 0;
+                for (int64_t t = o.block_begin; t < o.block_end; ++t, ++seq) {
+                    const int64_t lo = t * o.block;
+                    const int64_t hi = std::min<int64_t>(n, lo + o.block);
+                    const int par = int(seq & 1);
+                    const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
+                    if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
+                    launch_bin<CHORD, HULL>(lanes, s, p, b, reinterpret_cast<const float *>(x), bins, par, ovf,
+                                            ovf_flag + par, src, g, lo, hi, o.lambda, status);
+                    if (sample) {
+                        (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
+                        pl.prof_used[0]++;
+                        (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1]), s);
+                    }
+                    hipLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG), win_lds, s, p, lo,
+                                       int(hi - lo), bins, par, ovf, ovf_flag, reinterpret_cast<float *>(x), xlo, g,
+                                       zc, nzc, comp ? 1 : 0);
+                    if (sample) {
+                        (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1] + 1), s);
+                        pl.prof_used[1]++;
+                    }
+                }
+                return;
+            }
             if (pipe) {
                 const FusedBufs F = fused_bufs(pl, ws, x);
                 SlotDev slot[2] = {slot_at(wsb(ws) + L.total, o.block),
@@ -2043,8 +2506,14 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         reinterpret_cast<uint64_t>(p.gantry), reinterpret_cast<uint64_t>(b),
         reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
         uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
-        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes), uint64_t(fused) + 2 * uint64_t(pipe), bits_of(o.lambda),
+        uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes),
+        uint64_t(fused) + 2 * uint64_t(pipe) + 4 * uint64_t(binned) + 8 * uint64_t(comp), bits_of(o.lambda),
         0};
+    if (comp) {
+        // the compensation words start at zero in every call (outside the graph)
+        hipLaunchKernelGGL(k_zero_f32, dim3(unsigned(std::min<int64_t>(2048, (pl.nvox + 255) / 256))), dim3(256), 0, s,
+                           reinterpret_cast<float *>(wsb(ws) + L.lo), pl.nvox);
+    }
     return run_sweeps(pl, key, use_graph, o.n_iter, prof, s, sweep);
 }
 

@@ -156,7 +156,7 @@ def test_compute_calls_validate_before_device(plan):
 
 
 @pytest.mark.parametrize("field,value", [("block", 0), ("lambda_", 0.0), ("lambda_", float("inf")), ("n_iter", -1),
-                                         ("dtype", 3), ("chord", 9), ("flags", 0x20), ("block_begin", -1),
+                                         ("dtype", 3), ("chord", 9), ("flags", 0x80), ("block_begin", -1),
                                          ("block_end", 2), ("block_begin", 3), ("lanes", 2), ("lanes", 128),
                                          ("reserved", 1)])
 def test_drop_options_validated(plan, field, value):

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
+from _tol import rsp_err  # noqa: E402
 from paper_1802_01070_amd import api, synth  # noqa: E402
 from paper_1802_01070_amd.synth import Grid, MLPModel  # noqa: E402
 
@@ -263,8 +264,7 @@ def test_reentry_row_norm():
 # DROP
 # ---------------------------------------------------------------------------
 def rsp_close(got, ref, rel):
-    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
-    return err.max()
+    return rsp_err(got, ref).max()
 
 
 _drop1_ref = {}
@@ -508,24 +508,28 @@ def test_graph_replays_match_eager():
 
 
 def test_fp32_drop_is_bitwise_reproducible():
-    # the FP32 block accumulator is integer (fixed point + count), so repeated
-    # runs and a split resume give identical bits
+    # the FP32 block sums are integer (fixed point + count), so repeated runs
+    # give identical bits; without the compensation word (which lives for one
+    # call) a split resume does too
+    from paper_1802_01070_amd._lib import PCT_DROP_NO_COMPENSATION
     c = synth.WORKLOADS[2]
     sc = scan(2, 64000)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
-    runs = []
-    for _ in range(3):
-        x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
-        api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=2)
-        runs.append(x)
-    x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
-    api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_end=7)
-    api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_begin=7)
-    api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1)
-    runs.append(x)
-    for r in runs[1:]:
-        assert torch.equal(runs[0], r)
+    for flags in (0, PCT_DROP_NO_COMPENSATION):
+        runs = []
+        for _ in range(3):
+            x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+            api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=2, flags=flags)
+            runs.append(x)
+        if flags:
+            x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+            api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_end=7, flags=flags)
+            api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, block_begin=7, flags=flags)
+            api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=1, flags=flags)
+            runs.append(x)
+        for r in runs[1:]:
+            assert torch.equal(runs[0], r), flags
     assert_status_clean(plan)
 
 
@@ -535,7 +539,10 @@ def test_fused_commit_is_bitwise_the_separate_schedule():
     # of one block kernel + one commit kernel per block, for any number of
     # blocks (odd and even, to exercise the ping-pong and rotations), any
     # starting block, graph or per-block launches, and repeated sweeps
-    from paper_1802_01070_amd._lib import PCT_DROP_NO_GRAPH, PCT_DROP_SEPARATE_COMMIT
+    # (the binned schedule without its compensation word forms the same
+    # integer sums per voxel and commits them the same way: bitwise too)
+    from paper_1802_01070_amd._lib import (PCT_DROP_FUSED_COMMIT, PCT_DROP_NO_COMPENSATION, PCT_DROP_NO_GRAPH,
+                                           PCT_DROP_SEPARATE_COMMIT)
     c = synth.WORKLOADS[2]
     sc = scan(2, 64000)
     plan, pr = gpu_setup(sc)
@@ -550,9 +557,13 @@ def test_fused_commit_is_bitwise_the_separate_schedule():
                              block_end=end, lanes=lanes, flags=flags | PCT_DROP_SEPARATE_COMMIT)
         xf = x0.clone()
         api.pct_drop_iterate(plan, pr, b, xf, block=c.block, lam=c.lam, n_iter=iters, block_begin=begin,
-                             block_end=end, lanes=lanes, flags=flags)
+                             block_end=end, lanes=lanes, flags=flags | PCT_DROP_FUSED_COMMIT)
+        xb = x0.clone()
+        api.pct_drop_iterate(plan, pr, b, xb, block=c.block, lam=c.lam, n_iter=iters, block_begin=begin,
+                             block_end=end, lanes=lanes, flags=flags | PCT_DROP_NO_COMPENSATION)
         torch.cuda.synchronize()
         assert torch.equal(xs, xf), (xs - xf).abs().max().item()
+        assert torch.equal(xs, xb), (xs - xb).abs().max().item()
         assert not torch.equal(xf, x0)
     # the fused sweep leaves its accumulators clear: a following FP64 run on
     # the same workspace still matches the oracle
@@ -560,11 +571,12 @@ def test_fused_commit_is_bitwise_the_separate_schedule():
     api.pct_drop_iterate(plan, pr, b, xd, block=c.block, lam=c.lam, n_iter=1, block_end=4)
     ref = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=c.block, lam=c.lam, n_iter=1, blk_end=4)
     assert rsp_close(xd.cpu().numpy(), ref, 0) <= 1e-10
-    # and the fused path itself against the oracle on a short run
-    xf = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
-    api.pct_drop_iterate(plan, pr, b, xf, block=c.block, lam=c.lam, n_iter=1, block_end=5, lanes=64)
+    # and the fused and binned paths themselves against the oracle on a short run
     ref = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=c.block, lam=c.lam, n_iter=1, blk_end=5)
-    assert rsp_close(xf.double().cpu().numpy(), ref, 0) <= 1e-5
+    for flags in (PCT_DROP_FUSED_COMMIT, 0):
+        xf = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
+        api.pct_drop_iterate(plan, pr, b, xf, block=c.block, lam=c.lam, n_iter=1, block_end=5, lanes=64, flags=flags)
+        assert rsp_close(xf.double().cpu().numpy(), ref, 0) <= 1e-5, flags
     assert_status_clean(plan)
 
 
@@ -574,23 +586,26 @@ def test_traced_ahead_schedule_is_bitwise_the_fused_one():
     # bitwise that of the plain fused schedule and of the separate one, for
     # any block range, graph or per-block launches, repeated sweeps, and rows
     # that overflow a lane's stash (they are walked again)
-    from paper_1802_01070_amd._lib import PCT_DROP_NO_GRAPH, PCT_DROP_NO_TRACE_AHEAD, PCT_DROP_SEPARATE_COMMIT
+    from paper_1802_01070_amd._lib import (PCT_DROP_FUSED_COMMIT, PCT_DROP_NO_COMPENSATION, PCT_DROP_NO_GRAPH,
+                                           PCT_DROP_NO_TRACE_AHEAD, PCT_DROP_SEPARATE_COMMIT)
     c = synth.WORKLOADS[2]
     sc = scan(2, 64000)
     plan, pr = gpu_setup(sc)
     b = torch.from_numpy(sc.b).to(DEV)
     x0 = torch.from_numpy(np.random.default_rng(19).uniform(0.9, 1.1, sc.grid.nvox).astype(np.float32)).to(DEV)
+    traced, plain = PCT_DROP_FUSED_COMMIT, PCT_DROP_FUSED_COMMIT | PCT_DROP_NO_TRACE_AHEAD
     for begin, end, iters, flags in [(0, 1, 1, 0), (0, 2, 2, 0), (3, 6, 3, PCT_DROP_NO_GRAPH), (0, 7, 1, 0),
                                      (5, 20, 2, 0), (0, -1, 2, PCT_DROP_NO_GRAPH)]:
         say(f"  traced ahead vs fused: blocks [{begin},{end}) iters={iters} flags={flags}")
         out = []
-        for extra in (0, PCT_DROP_NO_TRACE_AHEAD, PCT_DROP_SEPARATE_COMMIT):
+        for extra in (traced, plain, PCT_DROP_SEPARATE_COMMIT, PCT_DROP_NO_COMPENSATION):
             x = x0.clone()
             api.pct_drop_iterate(plan, pr, b, x, block=c.block, lam=c.lam, n_iter=iters, block_begin=begin,
                                  block_end=end, lanes=64, flags=flags | extra)
             out.append(x)
         torch.cuda.synchronize()
-        assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+        for k in range(1, len(out)):
+            assert torch.equal(out[0], out[k]), k
     assert_status_clean(plan)
     # steep rows: non-monotone paths are walked whole by lane 0 and overflow
     # its stash, so every row goes through the walk-again branch
@@ -605,12 +620,12 @@ def test_traced_ahead_schedule_is_bitwise_the_fused_one():
     b_np = np.linspace(3.0, 9.0, len(rays)).astype(np.float32)
     b2 = torch.from_numpy(b_np).to(DEV)
     xs = []
-    for extra in (0, PCT_DROP_NO_TRACE_AHEAD):
+    for extra in (traced, plain, PCT_DROP_NO_COMPENSATION):
         x = torch.ones(grid.nvox, dtype=torch.float32, device=DEV)
         api.pct_drop_iterate(plan2, pr2, b2, x, block=4, lam=0.5, n_iter=2, lanes=64, flags=extra)
         xs.append(x)
     torch.cuda.synchronize()
-    assert torch.equal(xs[0], xs[1])
+    assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
     ref = oracle.drop(grid, mlp, pr_np, b_np, 1.0, block=4, lam=0.5, n_iter=2)
     assert rsp_close(xs[0].double().cpu().numpy(), ref, 0) <= 1e-5
     assert api.pct_device_status(plan2) & ~0x4 == 0

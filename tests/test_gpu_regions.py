@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+from _tol import rsp_err
 from oracle import regions as R
 from paper_1802_01070_amd import _lib, api, synth
 
@@ -173,7 +174,7 @@ def test_region_drop_matches_region_oracle(n_reg, halo, dtype, tol, hull):
     torch.cuda.synchronize()
     ref, info = R.region_drop(sc.grid, sc.mlp, sc.protons, sc.b, x0_used, n_reg, halo, c.block, c.lam, 2)
     assert [s["protons"].n for s in state] == [r[4] for r in info]
-    err = np.abs(x.double().cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0)
+    err = rsp_err(x.double().cpu().numpy(), ref)
     say(f"  max err {err.max():.3e}")
     assert err.max() <= tol
     for s in state:

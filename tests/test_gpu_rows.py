@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+from _tol import rsp_err
 from paper_1802_01070_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -100,7 +101,7 @@ def test_drop_over_stored_rows_matches_oracle(chord, lanes):
     torch.cuda.synchronize()
     ref = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=c.block, lam=c.lam, n_iter=2, mode=chord)
     got = x.double().cpu().numpy()
-    err = np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1.0))
+    err = np.max(rsp_err(got, ref))
     say(f"  vs oracle {err:.3e}; vs recomputed rows {(x - xr).abs().max().item():.3e}")
     assert err <= 1e-5
     assert (x - xr).abs().max().item() <= 1e-5
@@ -117,7 +118,7 @@ def test_stored_rows_ragged_blocks_resume_and_empty():
         x = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
         api.pct_drop_iterate_rows(plan, rows, b, x, block=B, lam=0.3, n_iter=2)
         ref = oracle.drop(sc.grid, sc.mlp, sc.protons, sc.b, 1.0, block=B, lam=0.3, n_iter=2, mode="f32")
-        err = np.max(np.abs(x.double().cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0))
+        err = np.max(rsp_err(x.double().cpu().numpy(), ref))
         assert err <= 1e-5, (B, err)
     # resume and bitwise reproducibility (integer block accumulator)
     x1 = torch.ones(sc.grid.nvox, dtype=torch.float32, device=DEV)
@@ -160,7 +161,7 @@ def test_stored_rows_full_size_sampled_blocks():
         sub = sc.subset(t * c.block, min(sc.m, (t + 1) * c.block))
         ref = oracle.drop(sc.grid, sc.mlp, sub.protons, sub.b, x_before, block=c.block, lam=c.lam, n_iter=1,
                           mode="f16")
-        err = np.max(np.abs(x.double().cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0))
+        err = np.max(rsp_err(x.double().cpu().numpy(), ref))
         say(f"  block {t}: max err {err:.3e}")
         assert err <= 1e-5
         done = t + 1

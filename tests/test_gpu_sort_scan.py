@@ -10,6 +10,7 @@ import pytest
 import torch
 
 from oracle import order as O
+from _tol import rsp_err
 from paper_1802_01070_amd import api, synth
 
 pytestmark = pytest.mark.gpu
@@ -109,7 +110,7 @@ def test_drop_on_the_device_sorted_scan_matches_oracle():
     torch.cuda.synchronize()
     opr, ob, _ = O.sort_scan(sc.grid, sc.protons, sc.b, cfg.n_angles, cfg.slab_mm)
     ref = oracle.drop(sc.grid, sc.mlp, opr, ob, 1.0, block=cfg.block, lam=cfg.lam, n_iter=2)
-    err = np.max(np.abs(x.double().cpu().numpy() - ref) / np.maximum(np.abs(ref), 1.0))
+    err = np.max(rsp_err(x.double().cpu().numpy(), ref))
     say(f"  max err {err:.3e}")
     assert err <= 1e-5
     assert api.pct_device_status(plan) == 0
