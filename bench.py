@@ -1,17 +1,20 @@
 """Benchmark of the fused MLP + DROP reconstruction path on one MI355X.
 
-Workload: the 200x200x32 (1 mm) cylinder scan with 10^7 protons over 180
-projection angles, DROP block 3200, lambda 0.1, FP32 RSP volume, 12 sweeps
-(one reconstruction).  One step is one DROP sweep over all 10^7 protons: for
-every block, each proton's most likely path is traced, a_i.x and ||a_i||^2
+Workload (default): the head-sized single-GPU share of a full scan, a
+256x256x64 grid of 1 mm voxels, ellipsoidal phantom with 10 spherical
+inserts, 5*10^7 protons over 360 projection angles sorted by angle, 4 mm slab
+of v_in and t_in, DROP block 6400, lambda 0.1, FP32 RSP volume, 8 sweeps (one
+reconstruction).  One step is one DROP sweep over all protons: for every
+block, each proton's most likely path is traced, a_i.x and ||a_i||^2
 computed, and the D-weighted back-projection committed.  Inputs are resident
-in HBM before the timed region starts.
+in HBM before the timed region starts.  --config 2 runs the 10^7-proton
+200x200x32 cylinder scan (block 3200, 12 sweeps) instead.
 
 Prints one JSON line:  value = proton-iterations/s, a roofline object for the
-dominant kernel (the fused block kernel) and the CPU oracle baseline measured
-on a bounded sample of the same scan.
+dominant kernel (the block kernel) and the CPU oracle baseline measured on a
+bounded sample of the same scan.
 
-    python bench.py [--gpus 1] [--steps 12] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 8] [--warmup 1] [--no-cpu-baseline]
 
 Two more workloads, each printing its own JSON line:
     --config 4   precision form: 2*10^7 protons on the 200x200x32 scan, 8
@@ -46,6 +49,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 BYTES_PER_PROTON = 40.0        # proton record: 9 float32 fields + b_i
 BYTES_PER_NONZERO = 8.0        # x_j gather (4 B) + back-projected contribution (4 B)
+RSP_FLOOR = 0.05               # RSP errors are relative to max(|x_oracle|, RSP_FLOOR)
 
 
 def log(msg):
@@ -55,12 +59,12 @@ def log(msg):
 # Sources each profiled kernel is built from: its counters stay valid while
 # these files are unchanged.
 KERNEL_SOURCES = {
-    "k_drop_pipe": ("pct_internal.h", "pct_path.hpp", "pct_kernels.hip"),
+    "k_drop": ("pct_internal.h", "pct_path.hpp", "pct_kernels.hip"),
     "fbp": ("pct_internal.h", "pct_fbp.hip"),
 }
 
 
-def kernel_sources_digest(kernel: str = "k_drop_pipe") -> str:
+def kernel_sources_digest(kernel: str = "k_drop") -> str:
     """sha256 over the HIP sources a profiled kernel is built from (the
     traffic counters are valid only for the kernels they were taken on)."""
     import hashlib
@@ -74,17 +78,17 @@ def kernel_sources_digest(kernel: str = "k_drop_pipe") -> str:
 
 def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of the block kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary of this workload, or None when the kernel
-    sources changed since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cyl200.json")
+    FETCH_SIZE / WRITE_SIZE summary of this workload and kernel, or None when
+    the kernel sources changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(p):
-        return None, "no counter summary"
+        return None, f"no counter summary for {kernel} on {workload}"
     t = json.load(open(p))
     if t.get("workload") != workload:
         return None, "counters taken on another workload"
     if t.get("sources_sha256") != kernel_sources_digest():
         return None, "kernel sources changed since the counters were taken"
-    return float(t["hbm_bytes_per_launch"]), p
+    return float(t["hbm_bytes_per_launch"]), os.path.relpath(p, ROOT)
 
 
 def measured_fbp_traffic(workload: str, kernel: str):
@@ -117,6 +121,18 @@ def count_nonzeros(api, plan, pr, chunk=1 << 20):
     return total
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks, hull=0.0, mode="none"):
     """FP64 oracle on the first n_blocks blocks of one sweep (from x0 = 1):
     throughput on the host cores and the RSP error of the GPU result on the
@@ -129,10 +145,11 @@ def cpu_baseline(sc, cfg, x_gpu_sample, n_blocks, hull=0.0, mode="none"):
     t0 = time.perf_counter()
     ref = oracle.drop(sc.grid, sc.mlp, sub.protons, sub.b, 1.0, block=cfg.block, lam=cfg.lam, n_iter=1, mode=mode)
     dt = time.perf_counter() - t0
-    err = np.abs(x_gpu_sample - ref) / np.maximum(np.abs(ref), 1.0)
+    err = np.abs(x_gpu_sample - ref) / np.maximum(np.abs(ref), RSP_FLOOR)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": m / dt, "unit": "proton-iterations/s", "cores": threads, "kind": "oracle",
+        "cpu_model": cpu_model(), "host_logical_cpus": os.cpu_count(),
         "sample": f"first {n_blocks} blocks ({m} protons) of one sweep of the same scan, FP64 C oracle, "
                   f"{dt:.1f} s" + ("" if mode == "none" else f", chords rounded to {mode}"),
     }, float(err.max()), float(err.mean())
@@ -184,7 +201,7 @@ def parallel_sweep_ceiling(api, plan, pr, x):
 
 def rsp_error(x, ref, touched):
     import torch
-    d = (x.double() - ref.double()).abs() / ref.double().abs().clamp_min(1.0)
+    d = (x.double() - ref.double()).abs() / ref.double().abs().clamp_min(RSP_FLOOR)
     d = d[touched]
     return float(d.max()), float(d.mean())
 
@@ -617,9 +634,9 @@ def run_fbp(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="2")
+    ap.add_argument("--config", default="3")
     ap.add_argument("--protons", type=int, default=0, help="override the number of protons")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-order", action="store_true", help="keep the acquisition order inside blocks")
@@ -629,6 +646,12 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per proton in the block kernel (0: automatic)")
     ap.add_argument("--no-drop-compare", action="store_true",
                     help="--config fbp: skip the DROP sweeps from x0 = 1 and from the FBP image")
+    ap.add_argument("--fused-commit", action="store_true",
+                    help="FP32: the atomic schedules (commit of block t-1 inside the launch of block t)")
+    ap.add_argument("--no-compensation", action="store_true",
+                    help="binned schedule: round x at every commit instead of carrying its rounding error")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the block kernels one by one on the stream instead of replaying a HIP graph")
     ap.add_argument("--separate-commit", action="store_true",
                     help="FP32: the separate schedule (block kernel, then a commit kernel per block)")
     ap.add_argument("--host-sort", action="store_true",
@@ -643,7 +666,8 @@ def main():
 
     import torch
     from paper_1802_01070_amd import api, synth
-    from paper_1802_01070_amd._lib import PCT_DROP_PROFILE, PCT_DROP_SEPARATE_COMMIT
+    from paper_1802_01070_amd._lib import (PCT_DROP_FUSED_COMMIT, PCT_DROP_NO_COMPENSATION, PCT_DROP_NO_GRAPH,
+                                           PCT_DROP_PROFILE, PCT_DROP_SEPARATE_COMMIT)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.config == "4":
@@ -698,7 +722,10 @@ def main():
         pr, b = box["o"]
         log(f"[bench] ordered blocks in {order_ms:.1f} ms")
     T = (m + cfg.block - 1) // cfg.block
-    sched = PCT_DROP_SEPARATE_COMMIT if args.separate_commit else 0
+    sched = ((PCT_DROP_SEPARATE_COMMIT if args.separate_commit else 0) |
+             (PCT_DROP_FUSED_COMMIT if args.fused_commit else 0) |
+             (PCT_DROP_NO_COMPENSATION if args.no_compensation else 0) |
+             (PCT_DROP_NO_GRAPH if args.no_graph else 0))
     log(f"[bench] sum of nonzeros {sum_nnz} ({sum_nnz / m:.1f} per proton), {T} blocks per sweep")
 
     # untimed warmup sweeps (the first run also compiles nothing: the library is prebuilt)
@@ -741,27 +768,34 @@ def main():
     k_sampled_ms = k_ms / max(k_n, 1)
     c_avg_ms = c_ms / max(c_n, 1)
     # Average launch of the block kernel over the timed region: the sweep's
-    # stream carries nothing else but one copy and one flush kernel per sweep
-    # (and, on the separate schedule, the per-block commit, timed apart).
+    # stream carries nothing else but one or two small kernels per sweep and,
+    # on the binned and separate schedules, the per-block commit kernel, whose
+    # average comes from the event-bracketed sample of the same stream.
     k_avg_ms = (ms_total / args.steps - (c_avg_ms * T if c_n else 0.0)) / T
     bytes_per_launch = (BYTES_PER_PROTON * m + BYTES_PER_NONZERO * sum_nnz) / T
     achieved_gbs = bytes_per_launch / (k_avg_ms * 1e-3) / 1e9
     whole_gbs = (BYTES_PER_PROTON * m + BYTES_PER_NONZERO * sum_nnz) * args.steps / (ms_total * 1e-3) / 1e9
     log(f"[bench] {ms_per_step:.1f} ms/step, block kernel avg {k_avg_ms * 1e3:.2f} us over the timed region, "
-        f"{k_sampled_ms * 1e3:.2f} us in {k_n} event-bracketed launches, "
-        f"separate commit avg {c_avg_ms * 1e3:.2f} us ({c_n} sampled); host wall {t_host:.2f} s")
+        f"{k_sampled_ms * 1e3:.2f} us in {k_n} event-timed launches, "
+        f"commit kernel avg {c_avg_ms * 1e3:.2f} us ({c_n} sampled); host wall {t_host:.2f} s")
 
     ceiling = parallel_sweep_ceiling(api, plan, pr, x)
     # which block schedule pct_drop_iterate takes (the library's rules): FP32
-    # with 64 lanes per proton, blocks of at most 4096 protons and a workspace
-    # sized for the block traces ahead; other FP32 runs fuse the commit; FP64
-    # runs the block kernel and a separate commit
+    # with lanes > 1 and blocks of at most 8192 protons: the binned schedule
+    # (block kernel + slab commit); with --fused-commit, 64 lanes per proton
+    # and blocks of at most 4096 protons the traced-ahead atomic schedule, else
+    # the fused one; FP64 runs the block kernel and a separate commit
     lanes = args.lanes or (64 if max(sc.grid.nx, sc.grid.ny) >= 160 else 32 if max(sc.grid.nx, sc.grid.ny) >= 64
                            else 16)
-    if vdtype == torch.float32 and lanes == 64 and cfg.block <= 4096 and not args.separate_commit:
+    f32 = vdtype == torch.float32
+    if f32 and lanes > 1 and cfg.block <= 8192 and not (args.separate_commit or args.fused_commit):
+        kname, kdesc = "k_drop_bin", ("k_drop_bin (MLP trace + a.x + |a|^2 + rho of block t, packed D-weighted "
+                                      "contributions stored into per-(slab, row) bins; the slab commit "
+                                      "k_slab_commit sums them in LDS and commits the touched voxels)")
+    elif f32 and lanes == 64 and cfg.block <= 4096 and not args.separate_commit:
         kname, kdesc = "k_drop_pipe", ("k_drop_pipe (trace of block t+1 into a row slot, DROP step of block t: "
                                        "a.x + |a|^2 + rho + D-weighted scatter, commit of block t-1)")
-    elif vdtype == torch.float32 and not args.separate_commit:
+    elif f32 and not args.separate_commit:
         kname, kdesc = "k_drop_fused", ("k_drop_fused (MLP trace + a.x + |a|^2 + rho + D-weighted scatter of "
                                         "block t, commit of block t-1)")
     else:
@@ -810,12 +844,15 @@ def main():
             "lanes_per_proton": args.lanes or "auto",
             "kernel_avg_us": k_avg_ms * 1e3,
             "kernel_avg_us_how": "timed region / block launches (HIP events on the sweep's stream)",
-            "kernel_avg_us_event_bracketed": k_sampled_ms * 1e3,
+            "kernel_avg_us_event_timed": k_sampled_ms * 1e3,
+            "kernel_avg_us_event_timed_how": ("a sample of the launches timed by HIP events: recorded by the launch "
+                                              "itself (hipExtLaunchKernelGGL) on the binned schedule, bracketing "
+                                              "the launch on the others"),
             "kernel_launches_sampled": k_n,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "whole_step_GBps": whole_gbs,
             "whole_step_frac": whole_gbs / HBM_PEAK_GBS,
-            "separate_commit_avg_us": c_avg_ms * 1e3 if c_n else None,
+            "commit_kernel_avg_us_event_timed": c_avg_ms * 1e3 if c_n else None,
         },
         "cpu_baseline": None,
         "parallel_sweep_ceiling": ceiling,

@@ -10,6 +10,7 @@
 //   k_drop_rows    the same with one lane per proton (very long paths)
 //   k_drop_commit  x_j += acc_j / s_j over the touched range, reset
 //   k_tv           smoothed total variation value and gradient
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -2164,10 +2165,13 @@ static int slab_window_words()
 }
 
 // Launch of block [lo, hi) of the binned schedule (see k_drop_bin).
+// With ev0/ev1 the launch records its own start and end in those events
+// (profiling: no extra stream packets around the kernel).
 template <int CHORD, bool HULL>
 static void launch_bin(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, const float *x,
                        const BinsDev &bins, int par, unsigned long long *ovf, int *ovf_flag, const PathSrc &src,
-                       const GridDev &g, int64_t lo, int64_t hi, double lambda, unsigned *status)
+                       const GridDev &g, int64_t lo, int64_t hi, double lambda, unsigned *status,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     const int64_t n = hi - lo;
     switch (lanes) {
@@ -2177,8 +2181,12 @@ static void launch_bin(int lanes, hipStream_t s, const ProtonsDev &p, const floa
             const int64_t n_wg = (n + (64 / LPP) - 1) / (64 / LPP);                                          \
             const unsigned grid = unsigned(8 * ((n_wg + 7) / 8));                                            \
             const size_t lds = size_t(64 / LPP) * 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<float>(); \
-            hipLaunchKernelGGL((k_drop_bin<CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, bins, par, \
-                               ovf, ovf_flag, src, g, lo, hi, lambda, status);                                  \
+            if (ev0)                                                                                             \
+                hipExtLaunchKernelGGL((k_drop_bin<CHORD, LPP, HULL>), dim3(grid), dim3(64), uint32_t(lds), s, ev0, \
+                                      ev1, 0u, p, b, x, bins, par, ovf, ovf_flag, src, g, lo, hi, lambda, status); \
+            else                                                                                                 \
+                hipLaunchKernelGGL((k_drop_bin<CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, bins,  \
+                                   par, ovf, ovf_flag, src, g, lo, hi, lambda, status);                         \
         }                                                                                                        \
         break;                                                                                                   \
     }
@@ -2425,22 +2433,28 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                     const int64_t lo = t * o.block;
                     const int64_t hi = std::min<int64_t>(n, lo + o.block);
                     const int par = int(seq & 1);
+                    // sampled blocks: both kernels timed by their own launch events
                     const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
-                    if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
-                    launch_bin<CHORD, HULL>(lanes, s, p, b, reinterpret_cast<const float *>(x), bins, par, ovf,
-                                            ovf_flag + par, src, g, lo, hi, o.lambda, status);
+                    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
                     if (sample) {
-                        (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
+                        e[0] = prof_event(pl, 0, 2 * pl.prof_used[0]);
+                        e[1] = prof_event(pl, 0, 2 * pl.prof_used[0] + 1);
+                        e[2] = prof_event(pl, 1, 2 * pl.prof_used[1]);
+                        e[3] = prof_event(pl, 1, 2 * pl.prof_used[1] + 1);
                         pl.prof_used[0]++;
-                        (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1]), s);
-                    }
-                    hipLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG), win_lds, s, p, lo,
-                                       int(hi - lo), bins, par, ovf, ovf_flag, reinterpret_cast<float *>(x), xlo, g,
-                                       zc, nzc, comp ? 1 : 0);
-                    if (sample) {
-                        (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1] + 1), s);
                         pl.prof_used[1]++;
                     }
+                    launch_bin<CHORD, HULL>(lanes, s, p, b, reinterpret_cast<const float *>(x), bins, par, ovf,
+                                            ovf_flag + par, src, g, lo, hi, o.lambda, status, e[0], e[1]);
+                    if (sample)
+                        hipExtLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG),
+                                              uint32_t(win_lds), s, e[2], e[3], 0u, p, lo, int(hi - lo), bins, par,
+                                              ovf, ovf_flag, reinterpret_cast<float *>(x), xlo, g, zc, nzc,
+                                              comp ? 1 : 0);
+                    else
+                        hipLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG), win_lds, s, p,
+                                           lo, int(hi - lo), bins, par, ovf, ovf_flag, reinterpret_cast<float *>(x),
+                                           xlo, g, zc, nzc, comp ? 1 : 0);
                 }
                 return;
             }
