@@ -71,7 +71,14 @@ extern "C" {
 #define PCT_DEV_ROW_OVERFLOW 0x1u
 #define PCT_DEV_NONFINITE 0x2u
 #define PCT_DEV_REENTRY 0x4u
-#define PCT_DEV_ACC_RANGE 0x8u /* a DROP contribution beyond the FP32 accumulator's fixed-point range */
+/* FP32 DROP: a contribution |rho_i a_ij| reached 2^12 (it is clamped to
+ * +-2^12; a NaN one counts as 0), or, on the binned schedule, the sum over a
+ * block's rows of their largest contribution reached 2^15, the bound past
+ * which a voxel's block sum may leave the +-2^15 range of the packed
+ * fixed-point word (sums are not checked one by one: x is exact only if none
+ * actually left it; the atomic schedules do not form this bound).  Use the
+ * FP64 value type, a smaller B or a smaller lambda for such data. */
+#define PCT_DEV_ACC_RANGE 0x8u
 #define PCT_DEV_BAD_ROW 0x10u  /* a stored row names a voxel outside the plan's grid (piece skipped) */
 
 /* ---- value and chord types --------------------------------------------- */
@@ -127,8 +134,14 @@ typedef struct {
 /* ---- plan --------------------------------------------------------------- */
 /* Host object holding the grid, the MLP model and its FP64 coefficient table
  * (one row per vertex: t_k = c0t t_in + c0th th_in + c2t t_out + c2th th_out).
- * Immutable after pct_plan_upload(); calls on different streams may share it
- * as long as each uses its own workspace. */
+ * Its geometry is fixed after pct_plan_create (pct_plan_set_hull aside, which
+ * needs no work in flight).  Calls on different threads and streams may share
+ * a plan as long as each uses its own workspace: pct_drop_iterate and
+ * pct_drop_iterate_rows keep a per-plan cache (the HIP graph of the last
+ * sweep, re-recorded when the call's buffers or options change, and the
+ * profiling events), and the plan's lock serialises their host-side enqueue;
+ * their device work on different streams may overlap.  pct_profile_read
+ * reports the last profiled call of any thread. */
 typedef struct pct_plan pct_plan;
 
 int pct_plan_create(const pct_grid *grid, const pct_mlp *mlp, pct_plan **out);
@@ -167,8 +180,9 @@ typedef struct {
     int32_t dtype;       /* pct_dtype of x.  FP64: FP64 block accumulator and count;
                             FP32: one 64-bit word per voxel with the row count and
                             the block sum in 2^-28 fixed point (order-independent,
-                            so results are bitwise reproducible); |block sum| must
-                            stay below 2^15 (PCT_DEV_ACC_RANGE otherwise)          */
+                            so results are bitwise reproducible); the block sum of
+                            a voxel must stay below 2^15 in magnitude: see
+                            PCT_DEV_ACC_RANGE                                      */
     int32_t chord;       /* pct_chord                                               */
     uint32_t flags;      /* PCT_DROP_* bits                                         */
     int64_t block_begin; /* first block of every sweep (>= 0)                       */
@@ -179,7 +193,7 @@ typedef struct {
 } pct_drop_opts;
 
 #define PCT_DROP_CHECK_FINITE 0x1u /* reserved: records and b are always checked      */
-/* B must be below 2^20 (the packed count field) for the FP32 value type. */
+/* B must be below 2^19 (the packed count field) for the FP32 value type. */
 #define PCT_DROP_NO_GRAPH 0x2u     /* launch per block on the stream, no HIP graph   */
 #define PCT_DROP_PROFILE 0x4u      /* bracket a sample of the per-block kernels with
                                       HIP events on `stream` (see pct_profile_read) */

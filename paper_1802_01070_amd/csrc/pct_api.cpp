@@ -438,7 +438,7 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
                      PCT_DROP_NO_TRACE_AHEAD | PCT_DROP_FUSED_COMMIT | PCT_DROP_NO_COMPENSATION))
         return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
-    if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 20)) return PCT_ERR_INVALID_ARG;
+    if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 19)) return PCT_ERR_INVALID_ARG;
     if (o->lanes != 0 && o->lanes != 1 && o->lanes != 8 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64)
         return PCT_ERR_INVALID_ARG;
     if (o->reserved != 0) return PCT_ERR_INVALID_ARG;
@@ -450,8 +450,11 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->n_iter == 0 || o->block_begin == end) return PCT_OK;
     pct_drop_opts oo = *o;
     oo.block_end = end;
-    return hip_status(
-        launch_drop(*const_cast<pct_plan *>(plan), protons_dev(p), p->n, b, x, oo, ws, ws_bytes, stream));
+    // the plan's geometry is immutable; its sweep-graph cache and profiling
+    // events are not, and calls sharing the plan take turns on them
+    pct_plan &pl = *const_cast<pct_plan *>(plan);
+    std::lock_guard<std::mutex> lock(pl.mu);
+    return hip_status(launch_drop(pl, protons_dev(p), p->n, b, x, oo, ws, ws_bytes, stream));
 }
 
 int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
@@ -500,7 +503,7 @@ int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const floa
     if (o->chord != rows->chord_type) return PCT_ERR_INVALID_ARG;
     if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT))
         return PCT_ERR_INVALID_ARG;
-    if (o->block >= (int64_t(1) << 20)) return PCT_ERR_INVALID_ARG;
+    if (o->block >= (int64_t(1) << 19)) return PCT_ERR_INVALID_ARG;
     if (o->lanes != 0 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64) return PCT_ERR_INVALID_ARG;
     if (o->reserved != 0) return PCT_ERR_INVALID_ARG;
     if (o->dtype != PCT_F32 || (o->flags & PCT_DROP_SEPARATE_COMMIT)) return PCT_ERR_UNSUPPORTED;
@@ -512,7 +515,9 @@ int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const floa
     if (o->n_iter == 0 || o->block_begin == end) return PCT_OK;
     pct_drop_opts oo = *o;
     oo.block_end = end;
-    return hip_status(launch_drop_rows(*const_cast<pct_plan *>(plan), *rows, b, static_cast<float *>(x), oo, ws,
+    pct_plan &pl = *const_cast<pct_plan *>(plan);
+    std::lock_guard<std::mutex> lock(pl.mu);
+    return hip_status(launch_drop_rows(pl, *rows, b, static_cast<float *>(x), oo, ws,
                                        stream));
 }
 
@@ -773,6 +778,7 @@ int pct_last_hip_error(void) { return g_last_hip_error; }
 int pct_profile_read(pct_plan *plan, double ms[2], int64_t launches[2])
 {
     if (!plan || !ms || !launches) return PCT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(plan->mu);
     return hip_status(profile_read(*plan, ms, launches));
 }
 

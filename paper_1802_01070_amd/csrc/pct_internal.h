@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "pct.h"
@@ -70,7 +71,8 @@ inline size_t slot_bytes(int64_t records) { return (size_t(records) * kSlotRecor
 // block's dominant axis and row of the block, kBinCap entries (a packed
 // 64-bit word each, the voxel index of entries 1.. in a second array) and, per
 // block parity, the voxel index of entry 0 with the entry count in its top
-// bits: 52 bytes per (slab, row).  Rows are rounded up to a multiple of 16;
+// bits: 52 bytes per (slab, row); then the largest contribution of every row
+// (one float per row).  Rows are rounded up to a multiple of 16;
 // blocks of the binned schedule hold at most kBinMaxRows rows.
 constexpr int kBinCap = 4;
 constexpr int kBinMaxRows = 8192;
@@ -79,7 +81,7 @@ inline int64_t bin_rows(int64_t records) { return (records + 15) & ~int64_t(15);
 inline size_t bin_bytes(int64_t records, int nslab)
 {
     const size_t nrow = size_t(nslab) * size_t(bin_rows(records));
-    return (nrow * (kBinCap * 8 + (kBinCap - 1) * 4 + 2 * 4) + 255) & ~size_t(255);
+    return (nrow * (kBinCap * 8 + (kBinCap - 1) * 4 + 2 * 4) + size_t(bin_rows(records)) * 4 + 255) & ~size_t(255);
 }
 
 // header words (int32 index): status word, then the [jmin, jmax] voxel range
@@ -111,6 +113,9 @@ FbpLayout fbp_layout(int64_t nbins);
 }  // namespace pct
 
 struct pct_plan {
+    // serialises the host-side enqueue of DROP calls that share the plan (its
+    // cached sweep graph, capture stream and profiling events)
+    std::mutex mu;
     pct_grid grid;
     pct_mlp mlp;
     int K;

@@ -194,21 +194,25 @@ __global__ void __launch_bounds__(kWG) k_backproject(ProtonsDev p, int64_t first
 // Block accumulator for the FP32 value type: one 64-bit word per voxel holding
 // the number of block rows that touch the voxel (bits 63..44) and the sum of
 // rho_i a_ij in fixed point with kFixBits fractional bits (two's complement in
-// the low bits).  One integer atomic per piece updates both, and integer
-// addition makes the block sum independent of the order of the atomics.  The
-// sum must stay below 2^(43 - kFixBits) in magnitude; larger single
-// contributions are clamped and raise PCT_DEV_ACC_RANGE.
+// the low bits).  One integer add per piece updates both, and integer
+// addition makes the block sum independent of the order of the adds.  The sum
+// must stay below kSumMax = 2^(43 - kFixBits) in magnitude.  A contribution of
+// kFixMax or more is clamped to it and raises PCT_DEV_ACC_RANGE, a NaN one
+// counts as zero.  The binned schedule also bounds every voxel's block sum by
+// the sum over the block's rows of their largest contribution and raises the
+// bit when that bound reaches kSumMax.
 constexpr int kFixBits = 28;
 constexpr int kCntShift = 44;
 constexpr double kFixScale = double(1u << kFixBits);
 constexpr double kFixMax = double(1u << 12);
+constexpr double kSumMax = double(1ull << (kCntShift - 1 - kFixBits));
 
 __device__ __forceinline__ unsigned long long pack_contribution(double v, bool first, unsigned *status)
 {
     if (!(fabs(v) < kFixMax)) {
         atomicOr(status, PCT_DEV_ACC_RANGE);
-        v = fmin(fmax(v, -kFixMax), kFixMax);
         if (v != v) v = 0.0;
+        else v = fmin(fmax(v, -kFixMax), kFixMax);
     }
     const long long q = llrint(v * kFixScale);
     return static_cast<unsigned long long>(q) + (first ? (1ull << kCntShift) : 0ull);
@@ -349,6 +353,14 @@ __device__ __forceinline__ double group_sum(double v)
 {
 #pragma unroll
     for (int off = LPP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int LPP>
+__device__ __forceinline__ double group_max(double v)
+{
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     return v;
 }
 
@@ -1032,6 +1044,7 @@ struct BinsDev {
     unsigned *j1;           // [slab][kBinCap - 1][cap]: voxel index of entries 1.. of each bin
     unsigned *j0;           // [parity][slab][cap]: voxel index of entry 0 | (entries - 1) << 30,
                             // kEmptyBin for a bin without entries
+    float *rowmax;          // [cap]: largest |rho_i a_ij| of each row of the block
     int cap;                // rows per block the bins hold (a multiple of 16)
     int nslab;              // max(nx, ny)
 };
@@ -1107,12 +1120,15 @@ struct BinScatterSink {
     unsigned *status;
     Reentry re;
     double rho;
+    double cmax;  // largest |rho a_ij| of the lane's pieces
     __device__ __forceinline__ void segment(double dx, double dy) { re.segment(dx, dy); }
     __device__ __forceinline__ void final(int j, int ix, int iy, int iz, double c)
     {
         bool first;
         re.visit(j, ix, iy, iz, c, first);
-        bw->put(j, pack_contribution(rho * c, first, status));
+        const double v = rho * c;
+        cmax = fmax(cmax, fabs(v));
+        bw->put(j, pack_contribution(v, first, status));
     }
 };
 
@@ -1122,6 +1138,7 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
            unsigned long long *ovf, int *ovf_flag, const PathSrc src, GridDev g, int64_t lo, int64_t hi,
            double lambda, unsigned *status)
 {
+    // also writes bins.rowmax[i - lo]: the row's largest |rho_i a_ij| (0 for a skipped row)
     using CT = float;
     extern __shared__ double lds[];
     constexpr int GPW = 64 / LPP;
@@ -1183,6 +1200,7 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
     }
     dot = group_sum<LPP>(dot);
     const double n2 = group_sum<LPP>(st.n2);
+    double cmax = 0.0;
     if (n2 > 0.0) {
         const double rho = lambda * (bi - dot) / n2;
         const int axis = block_axis(p, lo);
@@ -1190,17 +1208,22 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
         if (!spill) {
             for (int q = 0; q < ns; ++q) {
                 const int e = sj[q * 64 + lane];
-                bw.put(e & 0x7FFFFFFF, pack_contribution(rho * double(sc[q * 64 + lane]), e < 0, status));
+                const double v = rho * double(sc[q * 64 + lane]);
+                cmax = fmax(cmax, fabs(v));
+                bw.put(e & 0x7FFFFFFF, pack_contribution(v, e < 0, status));
             }
         } else {
-            BinScatterSink ss{&bw, status, {}, rho};
+            BinScatterSink ss{&bw, status, {}, rho, 0.0};
             ss.re.init(r);
             Merge<BinScatterSink, CHORD> m(ss, g);
             walk_lane<LPP>(gp, l, g, P, m);
             m.finish();
+            cmax = ss.cmax;
         }
         bw.flush();
     }
+    cmax = group_max<LPP>(cmax);
+    if (l == 0 && wg < n_wg && i < hi) bins.rowmax[i - lo] = float(cmax);
 }
 
 // Start of a binned sweep: every bin of both parities empty and both overflow
@@ -1246,7 +1269,7 @@ __device__ __forceinline__ void window_add(unsigned long long *win, unsigned j, 
 __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t lo, int nb, BinsDev bins, int par,
                                                          unsigned long long *ovf, int *ovf_flag,
                                                          float *__restrict__ x, float *__restrict__ xlo, GridDev g,
-                                                         int zc, int nzc, int comp)
+                                                         int zc, int nzc, int comp, unsigned *status)
 {
     extern __shared__ unsigned long long win[];
     const int tid = int(threadIdx.x);
@@ -1255,6 +1278,22 @@ __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t l
         uint4 *c2 = reinterpret_cast<uint4 *>(bins.j0 + (size_t(1 - par) * bins.nslab + s) * bins.cap);
         for (int q = tid; q < bins.cap / 4; q += kSlabWG) c2[q] = make_uint4(kEmptyBin, kEmptyBin, kEmptyBin, kEmptyBin);
         if (s == 0 && tid == 0) ovf_flag[1 - par] = 0;
+    }
+    if (blockIdx.x == 0) {
+        // every voxel's block sum is bounded by the sum over the rows of their
+        // largest contribution: past kSumMax a sum may have left the word's range
+        __shared__ double wsum[kSlabWG / 64];
+        double t = 0.0;
+        for (int q = tid; q < nb; q += kSlabWG) t += double(bins.rowmax[q]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if ((tid & 63) == 0) wsum[tid >> 6] = t;
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < kSlabWG / 64; ++w) tot += wsum[w];
+            if (!(tot < kSumMax)) atomicOr(status, PCT_DEV_ACC_RANGE);
+        }
     }
     const int axis = block_axis(p, lo);
     if (s >= g.n[axis]) return;
@@ -2417,6 +2456,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                 bins.w = reinterpret_cast<unsigned long long *>(bbase);
                 bins.j1 = reinterpret_cast<unsigned *>(bbase + nrow * kBinCap * 8);
                 bins.j0 = reinterpret_cast<unsigned *>(bbase + nrow * (kBinCap * 8 + (kBinCap - 1) * 4));
+                bins.rowmax = reinterpret_cast<float *>(bbase + nrow * (kBinCap * 8 + (kBinCap - 1) * 4 + 2 * 4));
                 bins.cap = int(cap);
                 bins.nslab = nslab;
                 const size_t ncnt = 2 * nrow;
@@ -2450,11 +2490,11 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                         hipExtLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG),
                                               uint32_t(win_lds), s, e[2], e[3], 0u, p, lo, int(hi - lo), bins, par,
                                               ovf, ovf_flag, reinterpret_cast<float *>(x), xlo, g, zc, nzc,
-                                              comp ? 1 : 0);
+                                              comp ? 1 : 0, status);
                     else
                         hipLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG), win_lds, s, p,
                                            lo, int(hi - lo), bins, par, ovf, ovf_flag, reinterpret_cast<float *>(x),
-                                           xlo, g, zc, nzc, comp ? 1 : 0);
+                                           xlo, g, zc, nzc, comp ? 1 : 0, status);
                 }
                 return;
             }
@@ -2752,5 +2792,6 @@ int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kWG), 0, s, partial, nblk, value_dev);
     return hipGetLastError();
 }
+
 
 }  // namespace pct

@@ -157,7 +157,7 @@ def test_compute_calls_validate_before_device(plan):
 
 @pytest.mark.parametrize("field,value", [("block", 0), ("lambda_", 0.0), ("lambda_", float("inf")), ("n_iter", -1),
                                          ("dtype", 3), ("chord", 9), ("flags", 0x80), ("block_begin", -1),
-                                         ("block_end", 2), ("block_begin", 3), ("lanes", 2), ("lanes", 128),
+                                         ("block_end", 2), ("block_begin", 3), ("lanes", 2), ("lanes", 128), ("block", 1 << 19),
                                          ("reserved", 1)])
 def test_drop_options_validated(plan, field, value):
     L = _lib.lib()
@@ -189,6 +189,7 @@ def test_tv_validation(plan):
     assert L.pct_tv(plan, C.c_void_p(8), 0, 0.0, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
     assert L.pct_tv(plan, C.c_void_p(8), 3, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
     assert L.pct_tv(plan, C.c_void_p(8), 0, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -2
+
 
 
 def test_region_layout_matches_the_papers_example():
