@@ -277,6 +277,19 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
 int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
            void *ws, size_t ws_bytes, void *stream);
 
+/* pct_tv for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * value and gradient, bitwise, with no workspace.  Its only scratch, the
+ * per-workgroup partial sums (at most 4096 doubles, 32 KB, whatever the
+ * grid), is a device array inside the library, one per GPU, held until the
+ * process ends; it allocates nothing.  Calls that overlap on one GPU share
+ * that array and race: serialise them (one stream per GPU, or events).  x,
+ * value_dev and grad as for pct_tv; plan need not be uploaded.  Errors:
+ * PCT_ERR_INVALID_ARG as pct_tv, PCT_ERR_HIP if the array's device address
+ * cannot be found on the current device (at most 64 devices). */
+int pct_tv_static(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
+                  void *stream);
+
 /* Within-block ordering.  Writes the records (and b, if not NULL) to out with
  * every block of `block` consecutive records sorted by (entry slice of v_in,
  * t_in, input position).  The DROP block update is a sum over the rows of the

@@ -27,7 +27,7 @@ FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out"
 
 EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan_table", "pct_workspace_size",
            "pct_plan_upload", "pct_device_status", "pct_mlp_trace", "pct_forward", "pct_backproject",
-           "pct_drop_iterate", "pct_tv", "pct_status_string", "pct_last_hip_error", "pct_profile_read",
+           "pct_drop_iterate", "pct_tv", "pct_tv_static", "pct_status_string", "pct_last_hip_error", "pct_profile_read",
            "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
            "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows",
            "pct_order_blocks", "pct_plan_set_hull", "pct_fbp_workspace_size", "pct_fbp_sinogram", "pct_fbp_filter",
@@ -105,6 +105,7 @@ def lib() -> C.CDLL:
             "pct_backproject": ([vp, P(pct_protons), vp, i32, vp, vp, sz, vp], C.c_int),
             "pct_drop_iterate": ([vp, P(pct_protons), vp, vp, P(pct_drop_opts), vp, sz, vp], C.c_int),
             "pct_tv": ([vp, vp, i32, C.c_double, vp, vp, vp, sz, vp], C.c_int),
+            "pct_tv_static": ([vp, vp, i32, C.c_double, vp, vp, vp], C.c_int),
             "pct_status_string": ([C.c_int], C.c_char_p),
             "pct_last_hip_error": ([], C.c_int),
             "pct_profile_read": ([vp, P(C.c_double), P(i64)], C.c_int),

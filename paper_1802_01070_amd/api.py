@@ -240,6 +240,19 @@ def pct_tv(plan: Plan, x: torch.Tensor, eps: float, with_grad: bool = True):
     return val, grad
 
 
+def pct_tv_static(plan: Plan, x: torch.Tensor, eps: float, with_grad: bool = True):
+    """pct_tv without a workspace (for callers that cannot allocate: the
+    library's own per-GPU scratch array holds the partial sums)."""
+    code = _dtype_code(x)
+    xp = _dev(x, "x", numel=plan.nvox)
+    val = torch.zeros(1, dtype=torch.float64, device=x.device)
+    grad = torch.empty_like(x) if with_grad else None
+    st = lib().pct_tv_static(plan.handle, xp, code, float(eps), C.c_void_p(val.data_ptr()),
+                             C.c_void_p(grad.data_ptr()) if with_grad else None, _stream(x.device))
+    check(st, "pct_tv_static")
+    return val, grad
+
+
 def pct_profile_read(plan: Plan):
     """(ms, launches) per kernel kind [fused block kernel, commit] of the last
     profiled pct_drop_iterate call."""

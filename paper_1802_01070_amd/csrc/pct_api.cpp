@@ -466,6 +466,13 @@ int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, doubl
     return hip_status(launch_tv(*plan, x, dtype, eps, value_dev, grad, ws, stream));
 }
 
+int pct_tv_static(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
+                  void *stream)
+{
+    if (!plan || !x || !value_dev || !finite_pos(eps) || !valid_dtype(dtype)) return PCT_ERR_INVALID_ARG;
+    return hip_status(launch_tv_static(*plan, x, dtype, eps, value_dev, grad, stream));
+}
+
 int pct_rows_count(const pct_plan *plan, const pct_protons *p, int64_t *offsets, void *ws, size_t ws_bytes,
                    void *stream)
 {

@@ -162,6 +162,8 @@ int launch_region_select(const pct_plan &pl, const ProtonsDev &p, int64_t n, con
                          void *stream);
 int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,
               void *stream);
+int launch_tv_static(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad,
+                     void *stream);
 int upload_table(const pct_plan &pl, void *ws, void *stream);
 int launch_fbp_sinogram(const FbpDev &f, const ProtonsDev &p, int64_t n, const float *b, unsigned long long *sum,
                         unsigned *cnt, double *proj, int32_t *count, void *stream);

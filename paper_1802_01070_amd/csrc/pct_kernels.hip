@@ -17,6 +17,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -2776,12 +2777,9 @@ int launch_drop_rows(pct_plan &pl, const pct_rows &rows, const float *b, float *
     return run_sweeps(pl, key, use_graph, o.n_iter, prof, s, sweep);
 }
 
-int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,
-              void *stream)
+static int tv_into(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad,
+                   double *partial, hipStream_t s)
 {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    Layout L = layout_for(pl.nvox, pl.K, dtype);
-    double *partial = reinterpret_cast<double *>(wsb(ws) + L.partial);
     int nblk = int(std::min<int64_t>(kMaxPartials, (pl.nvox + kWG - 1) / kWG));
     if (dtype == PCT_F64)
         hipLaunchKernelGGL(k_tv<double>, dim3(nblk), dim3(kWG), 0, s, static_cast<const double *>(x),
@@ -2793,5 +2791,52 @@ int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *
     return hipGetLastError();
 }
 
+int launch_tv(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad, void *ws,
+              void *stream)
+{
+    const Layout L = layout_for(pl.nvox, pl.K, dtype);
+    return tv_into(pl, x, dtype, eps, value_dev, grad, reinterpret_cast<double *>(wsb(ws) + L.partial),
+                   static_cast<hipStream_t>(stream));
+}
+
+// TV without a workspace: the per-workgroup partial sums (at most
+// kMaxPartials doubles, 32 KB) live in this file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes the array's
+// name to a kernel: its device address is looked up once per device (with
+// that device current) and kept.  Calls on one GPU share the array, so calls
+// that overlap on one GPU race; every partial a call reads it has written
+// first, so nothing needs clearing.
+static __device__ __align__(256) double scratch[kMaxPartials];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch[kMaxScratchDevices];
+
+static hipError_t scratch_address(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+int launch_tv_static(const pct_plan &pl, const void *x, int dtype, double eps, double *value_dev, void *grad,
+                     void *stream)
+{
+    double *partial = nullptr;
+    const hipError_t e = scratch_address(&partial);
+    if (e != hipSuccess) return e;
+    return tv_into(pl, x, dtype, eps, value_dev, grad, partial, static_cast<hipStream_t>(stream));
+}
 
 }  // namespace pct

@@ -189,7 +189,12 @@ def test_tv_validation(plan):
     assert L.pct_tv(plan, C.c_void_p(8), 0, 0.0, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
     assert L.pct_tv(plan, C.c_void_p(8), 3, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -1
     assert L.pct_tv(plan, C.c_void_p(8), 0, 1e-3, C.c_void_p(8), None, FAKE_WS, nb, None) == -2
-
+    # the variant without a workspace validates the same arguments (no launch here)
+    assert L.pct_tv_static(None, C.c_void_p(8), 0, 1e-3, C.c_void_p(8), None, None) == -1
+    assert L.pct_tv_static(plan, None, 0, 1e-3, C.c_void_p(8), None, None) == -1
+    assert L.pct_tv_static(plan, C.c_void_p(8), 0, 0.0, C.c_void_p(8), None, None) == -1
+    assert L.pct_tv_static(plan, C.c_void_p(8), 3, 1e-3, C.c_void_p(8), None, None) == -1
+    assert L.pct_tv_static(plan, C.c_void_p(8), 0, 1e-3, None, None, None) == -1
 
 
 def test_region_layout_matches_the_papers_example():
