@@ -506,7 +506,7 @@ static int64_t build_row(const orc_grid *g, const orc_mlp *m, const double *tab,
     free(ch);
     /* sort by (voxel, emission position), then sum each run of equal voxels in
      * emission order */
-    qsort(e, (size_t)n, sizeof(orc_entry), cmp_entry);
+    if (n > 1) qsort(e, (size_t)n, sizeof(orc_entry), cmp_entry);   /* an empty row has no buffer */
     int64_t nd = 0;
     for (int64_t q = 0; q < n; q++) {
         if (nd > 0 && e[nd - 1].j == e[q].j) e[nd - 1].a += e[q].a;
