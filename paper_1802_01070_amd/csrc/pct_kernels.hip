@@ -479,6 +479,128 @@ __device__ __forceinline__ void walk_lane(const GroupPath &gp, int l, const Grid
     }
 }
 
+// Table-path form of the group staging: LDS holds only the signed dominant
+// coordinate A(k) of every vertex (one double per vertex instead of three),
+// which is all the monotonicity check and the lanes' binary searches read; a
+// lane recomputes the full vertices of the segments it walks from the shared
+// table, with the same arithmetic, so the walk sees the same values.
+template <int LPP>
+__device__ __forceinline__ GroupPath stage_path_dom(const Rec &r, const PathSrc &src, const GridDev &g,
+                                                    double *__restrict__ A, int l, bool active)
+{
+    GroupPath gp;
+    gp.dom = fabs(r.cs) >= fabs(r.sn) ? 0 : 1;
+    const double e = gp.dom == 0 ? r.cs : r.sn;
+    gp.sgn = e > 0.0 ? 1.0 : -1.0;
+    const int K = src.K;
+    gp.K = K;
+    for (int k = l; k <= K; k += LPP) {
+        double v[3] = {0.0, 0.0, 0.0};
+        if (active) vertex(r, src.tab + k * kRowDoubles, v);
+        A[k] = gp.sgn * v[gp.dom];
+    }
+    __syncthreads();
+    bool bad = !active;
+    for (int k = l; k < K; k += LPP) bad |= !(A[k + 1] > A[k]);
+    gp.full = group_any<LPP>(bad);
+    gp.s_lo = 0;
+    gp.s_hi = -1;
+    if (gp.full) {
+        if (active) gp.s_hi = g.n[gp.dom] - 1;
+        return gp;
+    }
+    const int a = gp.dom;
+    const double c0 = gp.sgn * A[0], c1 = gp.sgn * A[K];  // sgn = +-1: the vertices' own coordinates
+    const double f0 = floor((fmin(c0, c1) - g.lo[a]) * g.inv_pitch[a]);
+    const double f1 = floor((fmax(c0, c1) - g.lo[a]) * g.inv_pitch[a]);
+    if (f1 < 0.0 || f0 > double(g.n[a] - 1)) return gp;
+    gp.s_lo = int(fmax(f0, 0.0));
+    gp.s_hi = int(fmin(f1, double(g.n[a] - 1)));
+    return gp;
+}
+
+// walk_lane over a stage_path_dom staging: the same slab range, start vertex
+// and stop test, with the segment end points recomputed from the table.
+template <int LPP, class M>
+__device__ __forceinline__ void walk_lane_dom(const GroupPath &gp, int l, const GridDev &g,
+                                              const double *__restrict__ A, const Rec &r, const PathSrc &src, M &m)
+{
+    const int K = gp.K;
+    const int a = gp.dom;
+    double p0[3], p1[3];
+    if (gp.full) {
+        if (l != 0 || gp.s_hi < gp.s_lo) return;
+        vertex(r, src.tab, p0);
+        for (int k = 0; k < K; ++k) {
+            vertex(r, src.tab + (k + 1) * kRowDoubles, p1);
+            m.segment(p1[0] - p0[0], p1[1] - p0[1]);
+            walk_segment_range(p0, p1, g, a, 0, g.n[a] - 1, m);
+            p0[0] = p1[0];
+            p0[1] = p1[1];
+            p0[2] = p1[2];
+        }
+        return;
+    }
+    const int ns = gp.s_hi - gp.s_lo + 1;
+    if (ns <= 0) return;
+    const int q = ns / LPP, rem = ns % LPP;
+    const int off = l * q + min(l, rem);
+    const int cntl = q + (l < rem ? 1 : 0);
+    if (cntl <= 0) return;
+    int s0, s1;
+    if (gp.sgn > 0.0) {
+        s0 = gp.s_lo + off;
+        s1 = s0 + cntl - 1;
+    } else {
+        s1 = gp.s_hi - off;
+        s0 = s1 - cntl + 1;
+    }
+    const double entry = gp.sgn > 0.0 ? g.lo[a] + s0 * g.pitch[a] : -(g.lo[a] + (s1 + 1) * g.pitch[a]);
+    const double exitc = gp.sgn > 0.0 ? g.lo[a] + (s1 + 1) * g.pitch[a] : -(g.lo[a] + s0 * g.pitch[a]);
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A[mid] <= entry) lo = mid;
+        else hi = mid - 1;
+    }
+    vertex(r, src.tab + lo * kRowDoubles, p0);
+    for (int k = lo; k < K; ++k) {
+        vertex(r, src.tab + (k + 1) * kRowDoubles, p1);
+        walk_segment_range(p0, p1, g, a, s0, s1, m);
+        if (A[k + 1] >= exitc) break;
+        p0[0] = p1[0];
+        p0[1] = p1[1];
+        p0[2] = p1[2];
+    }
+}
+
+// Staging and lane walk of the binned and separate-commit block kernels: hull
+// paths keep every vertex in LDS (a hull vertex costs two quadratures), table
+// paths only A(k).
+template <int LPP, bool HULL>
+__device__ __forceinline__ GroupPath stage_group(const Rec &r, const PathSrc &src, const GridDev &g, double *P,
+                                                 int l, bool active)
+{
+    if constexpr (HULL)
+        return stage_path<LPP, true>(r, src, g, P, l, active);
+    else
+        return stage_path_dom<LPP>(r, src, g, P, l, active);
+}
+
+template <int LPP, bool HULL, class M>
+__device__ __forceinline__ void walk_group_lane(const GroupPath &gp, int l, const GridDev &g, const double *P,
+                                                const Rec &r, const PathSrc &src, M &m)
+{
+    if constexpr (HULL)
+        walk_lane<LPP>(gp, l, g, P, m);
+    else
+        walk_lane_dom<LPP>(gp, l, g, P, r, src, m);
+}
+
+// Doubles of LDS a group's staging takes per vertex.
+template <bool HULL>
+constexpr int kStageDoubles = HULL ? 3 : 1;
+
 // Walk sink of the block kernel: tracks re-entries, accumulates ||a_i||^2 and
 // stashes the lane's merged pieces (voxel | first-visit bit, chord) in LDS,
 // entry-major so that the lanes of a wave hit different banks.
@@ -538,18 +660,18 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
         }
     }
     if (!active) r.cs = 1.0, r.sn = 0.0;
-    double *P = lds + grp * 3 * src.nvmax;
-    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * src.nvmax);
+    double *P = lds + grp * kStageDoubles<HULL> * src.nvmax;
+    char *stash = reinterpret_cast<char *>(lds + GPW * kStageDoubles<HULL> * src.nvmax);
     int *sj = reinterpret_cast<int *>(stash);
     CT *sc = reinterpret_cast<CT *>(stash + size_t(64) * kStash * sizeof(int));
-    const GroupPath gp = stage_path<LPP, HULL>(r, src, g, P, l, active);
+    const GroupPath gp = stage_group<LPP, HULL>(r, src, g, P, l, active);
 
     // one walk: ||a_i||^2, re-entries and the stash of pieces
     StashSink<CT, kStash> st{sj, sc, lane, {}, 0.0, 0};
     st.re.init(r);
     {
         Merge<StashSink<CT, kStash>, CHORD> m(st, g);
-        walk_lane<LPP>(gp, l, g, P, m);
+        walk_group_lane<LPP, HULL>(gp, l, g, P, r, src, m);
         m.finish();
     }
     if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
@@ -570,7 +692,7 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
         ds.n2 = 0.0;
         ds.re.init(r);
         Merge<DotSink<T>, CHORD> m(ds, g);
-        walk_lane<LPP>(gp, l, g, P, m);
+        walk_group_lane<LPP, HULL>(gp, l, g, P, r, src, m);
         m.finish();
         dot = ds.dot;
     }
@@ -604,7 +726,7 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
             sc2.jmax = -1;
             sc2.re.init(r);
             Merge<DropScatterSink<T>, CHORD> m(sc2, g);
-            walk_lane<LPP>(gp, l, g, P, m);
+            walk_group_lane<LPP, HULL>(gp, l, g, P, r, src, m);
             m.finish();
             jmin = sc2.jmin;
             jmax = sc2.jmax;
@@ -1164,17 +1286,17 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
         }
     }
     if (!active) r.cs = 1.0, r.sn = 0.0;
-    double *P = lds + grp * 3 * src.nvmax;
-    char *stash = reinterpret_cast<char *>(lds + GPW * 3 * src.nvmax);
+    double *P = lds + grp * kStageDoubles<HULL> * src.nvmax;
+    char *stash = reinterpret_cast<char *>(lds + GPW * kStageDoubles<HULL> * src.nvmax);
     int *sj = reinterpret_cast<int *>(stash);
     CT *sc = reinterpret_cast<CT *>(stash + size_t(64) * kStash * sizeof(int));
-    const GroupPath gp = stage_path<LPP, HULL>(r, src, g, P, l, active);
+    const GroupPath gp = stage_group<LPP, HULL>(r, src, g, P, l, active);
 
     StashSink<CT, kStash> st{sj, sc, lane, {}, 0.0, 0};
     st.re.init(r);
     {
         Merge<StashSink<CT, kStash>, CHORD> m(st, g);
-        walk_lane<LPP>(gp, l, g, P, m);
+        walk_group_lane<LPP, HULL>(gp, l, g, P, r, src, m);
         m.finish();
     }
     if (st.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
@@ -1195,7 +1317,7 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
         ds.n2 = 0.0;
         ds.re.init(r);
         Merge<DotSink<float>, CHORD> m(ds, g);
-        walk_lane<LPP>(gp, l, g, P, m);
+        walk_group_lane<LPP, HULL>(gp, l, g, P, r, src, m);
         m.finish();
         dot = ds.dot;
     }
@@ -1217,7 +1339,7 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
             BinScatterSink ss{&bw, status, {}, rho, 0.0};
             ss.re.init(r);
             Merge<BinScatterSink, CHORD> m(ss, g);
-            walk_lane<LPP>(gp, l, g, P, m);
+            walk_group_lane<LPP, HULL>(gp, l, g, P, r, src, m);
             m.finish();
             cmax = ss.cmax;
         }
@@ -2139,7 +2261,7 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
     case LPP: {                                                                                                  \
         if constexpr (!HULL || LPP == 64) {                                                                      \
             const unsigned grid = unsigned((n + (64 / LPP) - 1) / (64 / LPP));                                \
-            const size_t lds = size_t(64 / LPP) * 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<T>();  \
+            const size_t lds = size_t(64 / LPP) * kStageDoubles<HULL> * size_t(src.nvmax) * sizeof(double) + stash_bytes<T>(); \
             hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, acc, \
                                cnt, range, src, g, lo, hi, lambda, status);                                     \
         }                                                                                                        \
@@ -2220,7 +2342,8 @@ static void launch_bin(int lanes, hipStream_t s, const ProtonsDev &p, const floa
         if constexpr (!HULL || LPP == 64) {                                                                      \
             const int64_t n_wg = (n + (64 / LPP) - 1) / (64 / LPP);                                          \
             const unsigned grid = unsigned(8 * ((n_wg + 7) / 8));                                            \
-            const size_t lds = size_t(64 / LPP) * 3 * size_t(src.nvmax) * sizeof(double) + stash_bytes<float>(); \
+            const size_t lds = size_t(64 / LPP) * kStageDoubles<HULL> * size_t(src.nvmax) * sizeof(double) + \
+                               stash_bytes<float>();                                                      \
             if (ev0)                                                                                             \
                 hipExtLaunchKernelGGL((k_drop_bin<CHORD, LPP, HULL>), dim3(grid), dim3(64), uint32_t(lds), s, ev0, \
                                       ev1, 0u, p, b, x, bins, par, ovf, ovf_flag, src, g, lo, hi, lambda, status); \
