@@ -1181,6 +1181,19 @@ __device__ __forceinline__ int block_axis(const ProtonsDev &p, int64_t lo)
     return fabs(cs) >= fabs(sn) ? 0 : 1;
 }
 
+// Exact quotient floor(j / d) for j < 2^31 and 1 <= d < 2^30, from an FP64
+// product with inv = 1 / d: the product is within 2^-20 of j / d, so the
+// truncated quotient is off by at most one and one remainder test corrects
+// it (a handful of instructions instead of the integer division sequence).
+__device__ __forceinline__ unsigned udiv_exact(unsigned j, unsigned d, double inv)
+{
+    unsigned q = unsigned(double(j) * inv);
+    const int r = int(j - q * d);
+    if (r < 0) --q;
+    else if (r >= int(d)) ++q;
+    return q;
+}
+
 // One lane's pieces, in walk order (slab by slab in the direction of travel),
 // into the bins of row p of the block.  A slab's first entry is held until the
 // lane leaves the slab, then stored with the bin's entry count in the top bits
@@ -1195,6 +1208,7 @@ struct BinWriter {
     int cur, k;
     unsigned long long w0;
     unsigned j0;
+    double inv_nx, inv_ny;  // 1 / nx, 1 / ny
 
     __device__ __forceinline__ void overflow(unsigned j, unsigned long long w)
     {
@@ -1217,7 +1231,9 @@ struct BinWriter {
             overflow(j, w);
             return;
         }
-        const int s = axis == 0 ? int(j % unsigned(nx)) : int((j / unsigned(nx)) % unsigned(ny));
+        const unsigned row = udiv_exact(j, unsigned(nx), inv_nx);  // j / nx
+        const int s = axis == 0 ? int(j - row * unsigned(nx))
+                                : int(row - udiv_exact(row, unsigned(ny), inv_ny) * unsigned(ny));
         if (s != cur) {
             flush();
             cur = s;
@@ -1327,7 +1343,8 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
     if (n2 > 0.0) {
         const double rho = lambda * (bi - dot) / n2;
         const int axis = block_axis(p, lo);
-        BinWriter bw{bins, par, axis, g.n[0], g.n[1], int(i - lo), gp.full || gp.dom != axis, ovf, ovf_flag, -1, 0, 0ull, 0u};
+        BinWriter bw{bins,     par, axis, g.n[0], g.n[1], int(i - lo), gp.full || gp.dom != axis, ovf, ovf_flag, -1,
+                     0,        0ull, 0u,  1.0 / double(g.n[0]), 1.0 / double(g.n[1])};
         if (!spill) {
             for (int q = 0; q < ns; ++q) {
                 const int e = sj[q * 64 + lane];
@@ -1378,15 +1395,21 @@ __global__ void __launch_bounds__(256) k_zero_f32(float *v, int64_t n)
 constexpr int kRowsPerThread = 8;   // rows of a block per slab-commit thread
 constexpr int kCommitCells = 16;    // window cells per thread and pass of the commit
 
-__device__ __forceinline__ void window_add(unsigned long long *win, unsigned j, unsigned long long w, int axis,
-                                           int nlat, int z0, int z1, unsigned nx, unsigned nxy)
+// Window cell of voxel j in the slab's z range [z0, z1), or -1.
+__device__ __forceinline__ int window_cell(unsigned j, int axis, int nlat, int z0, int z1, unsigned nx, unsigned nxy,
+                                          double inv_nx, double inv_nxy)
 {
-    const unsigned iz = j / nxy;
+    const unsigned iz = udiv_exact(j, nxy, inv_nxy);
     const unsigned rr = j - iz * nxy;
-    const unsigned iy = rr / nx;
+    const unsigned iy = udiv_exact(rr, nx, inv_nx);
     const unsigned ix = rr - iy * nx;
     const int zz = int(iz) - z0;
-    if (zz >= 0 && int(iz) < z1) atomicAdd(&win[int(axis == 0 ? iy : ix) + nlat * zz], w);
+    return zz >= 0 && int(iz) < z1 ? int(axis == 0 ? iy : ix) + nlat * zz : -1;
+}
+
+__device__ __forceinline__ void window_add(unsigned long long *win, int cell, unsigned long long w)
+{
+    if (cell >= 0) atomicAdd(&win[cell], w);
 }
 
 __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t lo, int nb, BinsDev bins, int par,
@@ -1431,6 +1454,7 @@ __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t l
     const unsigned *j1 = bins.j1 + size_t(s) * (kBinCap - 1) * bins.cap;
     const int cap = bins.cap;
     const unsigned nx = unsigned(g.n[0]), nxy = unsigned(g.n[0]) * unsigned(g.n[1]);
+    const double inv_nx = 1.0 / double(nx), inv_nxy = 1.0 / double(nxy);
     unsigned jr[kRowsPerThread];
     unsigned long long wr[kRowsPerThread];
 #pragma unroll
@@ -1460,15 +1484,21 @@ __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t l
     for (int m = 0; m < kRowsPerThread; ++m) {
         if (jr[m] == kEmptyBin) continue;
         const int c = int(jr[m] >> 30) + 1;
-        window_add(win, jr[m] & 0x3FFFFFFFu, wr[m], axis, nlat, z0, z1, nx, nxy);
-        if (c >= 2) window_add(win, jb[m], wb[m], axis, nlat, z0, z1, nx, nxy);
+        window_add(win,
+                   window_cell(jr[m] & 0x3FFFFFFFu, axis, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy), wr[m]);
+        if (c >= 2)
+            window_add(win, window_cell(jb[m], axis, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy),
+                       wb[m]);
         for (int k = 2; k < c; ++k) {
             const int r = tid + m * kSlabWG;
-            window_add(win, j1[size_t(k - 1) * cap + r], w[size_t(k) * cap + r], axis, nlat, z0, z1, nx, nxy);
+            window_add(win,
+                       window_cell(j1[size_t(k - 1) * cap + r], axis, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy),
+                       w[size_t(k) * cap + r]);
         }
     }
     const bool of = ovf_flag[par] != 0;
     __syncthreads();
+    const double inv_nlat = 1.0 / double(nlat);
     for (int q0 = 0; q0 < nw; q0 += kCommitCells * kSlabWG) {
         int jv[kCommitCells];
         unsigned long long wv[kCommitCells];
@@ -1479,7 +1509,8 @@ __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t l
             jv[u] = -1;
             wv[u] = 0ull;
             if (q < nw) {
-                const int a = q % nlat, zz = z0 + q / nlat;
+                const unsigned zq = udiv_exact(unsigned(q), unsigned(nlat), inv_nlat);
+                const int a = q - int(zq) * nlat, zz = z0 + int(zq);
                 const int ix = axis == 0 ? s : a, iy = axis == 0 ? a : s;
                 jv[u] = ix + g.n[0] * (iy + g.n[1] * zz);
                 wv[u] = win[q];
