@@ -66,6 +66,7 @@ extern "C" {
 #define PCT_ERR_REENTRY (-5)       /* (device) a voxel re-entry outside the kernel window */
 #define PCT_ERR_HIP (-6)           /* a HIP runtime call failed (see pct_last_hip_error)  */
 #define PCT_ERR_UNSUPPORTED (-7)   /* valid request this build does not implement         */
+#define PCT_ERR_CANCELLED (-8)     /* (device) a cancellable DROP call stopped on request */
 
 /* device status bits returned by pct_device_status() */
 #define PCT_DEV_ROW_OVERFLOW 0x1u
@@ -80,6 +81,7 @@ extern "C" {
  * FP64 value type, a smaller B or a smaller lambda for such data. */
 #define PCT_DEV_ACC_RANGE 0x8u
 #define PCT_DEV_BAD_ROW 0x10u  /* a stored row names a voxel outside the plan's grid (piece skipped) */
+#define PCT_DEV_CANCELLED 0x20u /* a cancellable DROP call stopped at a block boundary on request */
 
 /* ---- value and chord types --------------------------------------------- */
 typedef enum {
@@ -229,6 +231,12 @@ typedef struct {
  * bitwise those of the other atomic schedules.  This flag asks for the plain
  * fused schedule. */
 #define PCT_DROP_NO_TRACE_AHEAD 0x10u
+/* Cancellable call: the block steps stop at the first block boundary after a
+ * pct_drop_cancel request on this workspace (see there).  The call runs the
+ * binned schedule when it would otherwise (FP32), else the separate schedule
+ * (FP64, or FP32 without the bins' workspace); the fused and traced-ahead
+ * atomic schedules, whose launches commit the previous block, are not used. */
+#define PCT_DROP_CANCELLABLE 0x80u
 
 /* Workspace bytes for this plan and x of type dtype.  n > 0 adds, for DROP
  * blocks of up to n protons, two row slots (the traced-ahead schedule,
@@ -269,6 +277,28 @@ int pct_backproject(const pct_plan *plan, const pct_protons *p, const void *r, i
  * block_end) updating x in place.  b: float[n]; x: dtype[nvox]. */
 int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b, void *x,
                      const pct_drop_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/* Cancellation of DROP calls made with PCT_DROP_CANCELLABLE (a host-settable
+ * request checked between block steps).  request != 0 asks the calls running
+ * or queued on this workspace to stop: the block step whose commit sees the
+ * request is the last one applied (x holds every block step before it, each
+ * whole, and nothing after it; later sweeps of the call do nothing).  The
+ * request stays until pct_drop_cancel(..., 0) clears it, so a cancellable
+ * call started while it is set applies one block step.  The word is written
+ * on a private stream of the plan and the call returns once it is written;
+ * it does not wait for the DROP.  Calls without the flag ignore the request.
+ * PCT_ERR_INVALID_ARG for a missing plan or workspace, PCT_ERR_WORKSPACE for
+ * one that is too small, PCT_ERR_HIP if the write fails. */
+int pct_drop_cancel(pct_plan *plan, void *ws, size_t ws_bytes, int32_t request);
+
+/* Progress of the last cancellable DROP call on this workspace; synchronises
+ * `stream` first.  *blocks_done receives the block steps it applied, counted
+ * over all its sweeps (sweep s, block t of [block_begin, block_end) is step
+ * s * (block_end - block_begin) + (t - block_begin) + 1).  Returns PCT_OK when
+ * the call ran to its end, PCT_ERR_CANCELLED when it stopped on request; to
+ * resume, run the rest of the interrupted sweep (block_begin moved past the
+ * applied steps) and then the remaining sweeps. */
+int pct_drop_progress(const pct_plan *plan, void *ws, size_t ws_bytes, int64_t *blocks_done, void *stream);
 
 /* Smoothed total variation (differentiation form): TV(x) = sum_v sqrt(dx^2 +
  * dy^2 + dz^2 + eps^2) with forward differences, zero at the last index of
@@ -375,7 +405,8 @@ int pct_rows_build(const pct_plan *plan, const pct_protons *p, int32_t chord_typ
 /* Block-iterative DROP over stored rows: as pct_drop_iterate, with the rows
  * read instead of traced.  FP32 x only (PCT_ERR_UNSUPPORTED otherwise);
  * opts->chord must equal rows->chord_type; opts->lanes: 0 (64), 16, 32 or 64
- * lanes per row; PCT_DROP_SEPARATE_COMMIT is not supported. */
+ * lanes per row; PCT_DROP_SEPARATE_COMMIT and PCT_DROP_CANCELLABLE are not
+ * supported (PCT_ERR_UNSUPPORTED). */
 int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const float *b, void *x,
                           const pct_drop_opts *opts, void *ws, size_t ws_bytes, void *stream);
 

@@ -22,7 +22,10 @@ PCT_DROP_SEPARATE_COMMIT = 0x8
 PCT_DROP_NO_TRACE_AHEAD = 0x10
 PCT_DROP_FUSED_COMMIT = 0x20
 PCT_DROP_NO_COMPENSATION = 0x40
-DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range", 0x10: "bad_row"}
+PCT_DROP_CANCELLABLE = 0x80
+PCT_ERR_CANCELLED = -8
+DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range", 0x10: "bad_row",
+            0x20: "cancelled"}
 FIELDS = ("t_in", "v_in", "th_in", "ph_in", "t_out", "v_out", "th_out", "ph_out", "gantry")
 
 EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan_table", "pct_workspace_size",
@@ -31,7 +34,8 @@ EXPORTS = ("pct_plan_create", "pct_plan_destroy", "pct_plan_segments", "pct_plan
            "pct_region_layout", "pct_plan_region", "pct_region_select", "pct_select_slices",
            "pct_slice_span_histogram", "pct_rows_count", "pct_rows_build", "pct_drop_iterate_rows",
            "pct_order_blocks", "pct_plan_set_hull", "pct_fbp_workspace_size", "pct_fbp_sinogram", "pct_fbp_filter",
-           "pct_fbp_backproject", "pct_fbp", "pct_sort_scan_workspace_size", "pct_sort_scan")
+           "pct_fbp_backproject", "pct_fbp", "pct_sort_scan_workspace_size", "pct_sort_scan", "pct_drop_cancel",
+           "pct_drop_progress")
 
 
 class PctError(RuntimeError):
@@ -104,6 +108,8 @@ def lib() -> C.CDLL:
             "pct_forward": ([vp, P(pct_protons), vp, i32, vp, vp, vp, sz, vp], C.c_int),
             "pct_backproject": ([vp, P(pct_protons), vp, i32, vp, vp, sz, vp], C.c_int),
             "pct_drop_iterate": ([vp, P(pct_protons), vp, vp, P(pct_drop_opts), vp, sz, vp], C.c_int),
+            "pct_drop_cancel": ([vp, vp, sz, i32], C.c_int),
+            "pct_drop_progress": ([vp, vp, sz, P(i64), vp], C.c_int),
             "pct_tv": ([vp, vp, i32, C.c_double, vp, vp, vp, sz, vp], C.c_int),
             "pct_tv_static": ([vp, vp, i32, C.c_double, vp, vp, vp], C.c_int),
             "pct_status_string": ([C.c_int], C.c_char_p),

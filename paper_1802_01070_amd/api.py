@@ -184,6 +184,22 @@ def pct_drop_iterate(plan: Plan, p: Protons, b: torch.Tensor, x: torch.Tensor, b
     return x
 
 
+def pct_drop_cancel(plan: Plan, request: bool = True) -> None:
+    """Ask the cancellable DROP calls on the plan's workspace to stop at the
+    next block boundary (request False clears the request)."""
+    check(lib().pct_drop_cancel(plan.handle, plan.ws_ptr, plan.ws_bytes, int(bool(request))), "pct_drop_cancel")
+
+
+def pct_drop_progress(plan: Plan):
+    """(block steps applied, stopped on request) of the last cancellable DROP
+    call on the plan's workspace; synchronises the device's current stream."""
+    done = C.c_int64()
+    st = lib().pct_drop_progress(plan.handle, plan.ws_ptr, plan.ws_bytes, C.byref(done), _stream(plan.device))
+    if st not in (_lib.PCT_OK, _lib.PCT_ERR_CANCELLED):
+        check(st, "pct_drop_progress")
+    return done.value, st == _lib.PCT_ERR_CANCELLED
+
+
 class Rows:
     """Stored CSR rows of a proton set (pct_rows_count + pct_rows_build):
     chord lengths in FP32, FP16 or BF16, traced once on the GPU."""

@@ -303,6 +303,7 @@ int pct_plan_create(const pct_grid *grid, const pct_mlp *mlp, pct_plan **out)
     pl->prof_used[0] = pl->prof_used[1] = 0;
     pl->graph_exec = nullptr;
     pl->capture_stream = nullptr;
+    pl->cancel_stream = nullptr;
     if (!build_table(*pl)) {
         delete pl;
         return PCT_ERR_INVALID_ARG;
@@ -435,7 +436,8 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
     if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
     if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT |
-                     PCT_DROP_NO_TRACE_AHEAD | PCT_DROP_FUSED_COMMIT | PCT_DROP_NO_COMPENSATION))
+                     PCT_DROP_NO_TRACE_AHEAD | PCT_DROP_FUSED_COMMIT | PCT_DROP_NO_COMPENSATION |
+                     PCT_DROP_CANCELLABLE))
         return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
     if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 19)) return PCT_ERR_INVALID_ARG;
@@ -447,7 +449,8 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->block_begin < 0 || end > T || o->block_begin > end) return PCT_ERR_INVALID_ARG;
     st = check_ws(plan, ws, ws_bytes, o->dtype);
     if (st) return st;
-    if (o->n_iter == 0 || o->block_begin == end) return PCT_OK;
+    if (o->n_iter == 0 || o->block_begin == end)
+        return (o->flags & PCT_DROP_CANCELLABLE) ? hip_status(launch_gate_reset(*plan, ws, stream)) : PCT_OK;
     pct_drop_opts oo = *o;
     oo.block_end = end;
     // the plan's geometry is immutable; its sweep-graph cache and profiling
@@ -455,6 +458,25 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     pct_plan &pl = *const_cast<pct_plan *>(plan);
     std::lock_guard<std::mutex> lock(pl.mu);
     return hip_status(launch_drop(pl, protons_dev(p), p->n, b, x, oo, ws, ws_bytes, stream));
+}
+
+int pct_drop_cancel(pct_plan *plan, void *ws, size_t ws_bytes, int32_t request)
+{
+    if (!plan || !ws) return PCT_ERR_INVALID_ARG;
+    int st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    return hip_status(write_cancel(*plan, ws, request));
+}
+
+int pct_drop_progress(const pct_plan *plan, void *ws, size_t ws_bytes, int64_t *blocks_done, void *stream)
+{
+    if (!plan || !ws || !blocks_done) return PCT_ERR_INVALID_ARG;
+    int st = check_ws(plan, ws, ws_bytes, PCT_F32);
+    if (st) return st;
+    int halted = 0;
+    st = hip_status(read_progress(*plan, ws, blocks_done, &halted, stream));
+    if (st) return st;
+    return halted ? PCT_ERR_CANCELLED : PCT_OK;
 }
 
 int pct_tv(const pct_plan *plan, const void *x, int32_t dtype, double eps, double *value_dev, void *grad,
@@ -508,12 +530,14 @@ int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const floa
     if (rows->n > 0 && (!rows->offsets || !rows->vox || !rows->chord || !rows->n2 || !b)) return PCT_ERR_INVALID_ARG;
     if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
     if (o->chord != rows->chord_type) return PCT_ERR_INVALID_ARG;
-    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT))
+    if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT |
+                     PCT_DROP_CANCELLABLE))
         return PCT_ERR_INVALID_ARG;
     if (o->block >= (int64_t(1) << 19)) return PCT_ERR_INVALID_ARG;
     if (o->lanes != 0 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64) return PCT_ERR_INVALID_ARG;
     if (o->reserved != 0) return PCT_ERR_INVALID_ARG;
-    if (o->dtype != PCT_F32 || (o->flags & PCT_DROP_SEPARATE_COMMIT)) return PCT_ERR_UNSUPPORTED;
+    if (o->dtype != PCT_F32 || (o->flags & (PCT_DROP_SEPARATE_COMMIT | PCT_DROP_CANCELLABLE)))
+        return PCT_ERR_UNSUPPORTED;
     int64_t T = rows->n > 0 ? (rows->n + o->block - 1) / o->block : 0;
     int64_t end = o->block_end < 0 ? T : o->block_end;
     if (o->block_begin < 0 || end > T || o->block_begin > end) return PCT_ERR_INVALID_ARG;
@@ -776,6 +800,7 @@ const char *pct_status_string(int status)
     case PCT_ERR_REENTRY: return "voxel re-entry outside the kernel's window";
     case PCT_ERR_HIP: return "HIP runtime error";
     case PCT_ERR_UNSUPPORTED: return "unsupported request";
+    case PCT_ERR_CANCELLED: return "stopped on a cancel request";
     default: return "unknown status";
     }
 }

@@ -86,9 +86,22 @@ inline size_t bin_bytes(int64_t records, int nslab)
 
 // header words (int32 index): status word, then the [jmin, jmax] voxel range
 // touched by a block, double-buffered by block parity (FP64 path), four
-// rotating range slots of the fused FP32 path, and the two overflow flags of
-// the binned schedule (by block parity)
-enum : int { kHdrStatus = 0, kHdrRange0 = 2, kHdrRange1 = 4, kHdrSlots = 8, kHdrOvf = 16 };
+// rotating range slots of the fused FP32 path, the two overflow flags of the
+// binned schedule (by block parity), and the block-boundary gate of
+// cancellable calls: the host's cancel request, the gate word, the count of
+// ended workgroups of the running commit launch and (int64) the block steps
+// applied
+enum : int {
+    kHdrStatus = 0,
+    kHdrRange0 = 2,
+    kHdrRange1 = 4,
+    kHdrSlots = 8,
+    kHdrOvf = 16,
+    kHdrCancel = 20,
+    kHdrHalt = 21,
+    kHdrGateCount = 22,
+    kHdrDone = 24
+};
 
 Layout layout_for(int64_t nvox, int K, int dtype);
 
@@ -130,6 +143,7 @@ struct pct_plan {
     void *graph_exec;
     std::vector<uint64_t> graph_key;
     void *capture_stream;  // private hipStream_t used only to record the graph
+    void *cancel_stream;   // private hipStream_t that writes cancel requests
     int hull;              // 1: per-proton MLP between the hull entry and exit points
     double hull_c[2], hull_r;
 };
@@ -174,6 +188,9 @@ int profile_read(pct_plan &pl, double ms[2], int64_t launches[2]);
 void profile_release(pct_plan &pl);
 void graph_release(pct_plan &pl);
 int read_status(const pct_plan &pl, void *ws, int reset, uint32_t *bits, void *stream);
+int write_cancel(pct_plan &pl, void *ws, int32_t request);
+int read_progress(const pct_plan &pl, void *ws, int64_t *done, int *halted, void *stream);
+int launch_gate_reset(const pct_plan &pl, void *ws, void *stream);
 
 GridDev grid_dev(const pct_grid &g);
 

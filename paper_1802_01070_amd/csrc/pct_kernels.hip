@@ -33,6 +33,50 @@ __device__ __forceinline__ void raise_status(unsigned *status, unsigned bit)
     atomicOr(status, bit);
 }
 
+// Block-boundary gate of a cancellable DROP call (workspace header words).
+// Every per-block kernel returns at once while the gate is closed; the last
+// workgroup of each commit launch counts the block step and, when the host
+// has requested a stop, closes the gate for the launches after it.  The
+// gate word changes only there, after every workgroup of that launch has
+// read it, so all workgroups of a launch take the same decision.
+struct GateDev {
+    int *halt;          // nullptr: the call is not cancellable
+    unsigned *wg_done;  // workgroups of the running commit launch that ended
+    const int *cancel;  // the host's request
+    long long *done;    // block steps applied by the call
+    unsigned *status;
+};
+
+__device__ __forceinline__ bool gate_closed(const int *halt) { return halt && *halt != 0; }
+
+__device__ __forceinline__ void gate_commit_end(const GateDev &gt)
+{
+    if (!gt.halt) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned k = atomicAdd(gt.wg_done, 1u);
+        if (k == gridDim.x - 1) {
+            *gt.wg_done = 0u;
+            *gt.done += 1;
+            if (__hip_atomic_load(gt.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0) {
+                *gt.halt = 1;
+                atomicOr(gt.status, PCT_DEV_CANCELLED);
+            }
+        }
+    }
+}
+
+// Start of a cancellable call: gate open, no block step applied.
+__global__ void k_gate_begin(GateDev gt)
+{
+    if (threadIdx.x == 0) {
+        *gt.halt = 0;
+        *gt.wg_done = 0u;
+        *gt.done = 0;
+    }
+}
+
 // Merges consecutive pieces in the same voxel and hands merged pieces (with
 // the chord rounded to the solver's format) to Inner::final.
 template <class Inner, int CHORD>
@@ -290,8 +334,9 @@ template <typename T, int CHORD, bool HULL>
 __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__restrict__ b,
                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
                                                    const PathSrc src,  GridDev g, int64_t lo,
-                                                   int64_t hi, double lambda, unsigned *status)
+                                                   int64_t hi, double lambda, unsigned *status, const int *halt)
 {
+    if (gate_closed(halt)) return;
     int64_t i = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     bool active = i < hi;
     Rec r{};
@@ -639,8 +684,9 @@ template <typename T, int CHORD, int LPP, bool HULL>
 __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__restrict__ b,
                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
                                                    const PathSrc src,  GridDev g, int64_t lo,
-                                                   int64_t hi, double lambda, unsigned *status)
+                                                   int64_t hi, double lambda, unsigned *status, const int *halt)
 {
+    if (gate_closed(halt)) return;
     using CT = typename std::conditional<sizeof(T) == 4, float, double>::type;
     extern __shared__ double lds[];
     constexpr int GPW = 64 / LPP;  // proton groups per workgroup
@@ -1275,8 +1321,9 @@ template <int CHORD, int LPP, bool HULL>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ x, BinsDev bins, int par,
            unsigned long long *ovf, int *ovf_flag, const PathSrc src, GridDev g, int64_t lo, int64_t hi,
-           double lambda, unsigned *status)
+           double lambda, unsigned *status, const int *halt)
 {
+    if (gate_closed(halt)) return;
     // also writes bins.rowmax[i - lo]: the row's largest |rho_i a_ij| (0 for a skipped row)
     using CT = float;
     extern __shared__ double lds[];
@@ -1412,10 +1459,10 @@ __device__ __forceinline__ void window_add(unsigned long long *win, int cell, un
     if (cell >= 0) atomicAdd(&win[cell], w);
 }
 
-__global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t lo, int nb, BinsDev bins, int par,
-                                                         unsigned long long *ovf, int *ovf_flag,
-                                                         float *__restrict__ x, float *__restrict__ xlo, GridDev g,
-                                                         int zc, int nzc, int comp, unsigned *status)
+__device__ __forceinline__ void slab_commit_body(const ProtonsDev &p, int64_t lo, int nb, const BinsDev &bins,
+                                                 int par, unsigned long long *ovf, int *ovf_flag,
+                                                 float *__restrict__ x, float *__restrict__ xlo, const GridDev &g,
+                                                 int zc, int nzc, int comp, unsigned *status)
 {
     extern __shared__ unsigned long long win[];
     const int tid = int(threadIdx.x);
@@ -1555,12 +1602,22 @@ __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t l
     }
 }
 
+__global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t lo, int nb, BinsDev bins, int par,
+                                                         unsigned long long *ovf, int *ovf_flag,
+                                                         float *__restrict__ x, float *__restrict__ xlo, GridDev g,
+                                                         int zc, int nzc, int comp, unsigned *status, GateDev gt)
+{
+    if (gate_closed(gt.halt)) return;
+    slab_commit_body(p, lo, nb, bins, par, ovf, ovf_flag, x, xlo, g, zc, nzc, comp, status);
+    gate_commit_end(gt);
+}
+
 // Commit of one block: a dense, coalesced scan of the block's touched index
 // range; voxels with a non-zero row count get x_j += acc_j / s_j and are reset.
 // Also re-arms the range words of the next block.
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_drop_commit(T *x, void *accv, int32_t *cnt, const int *range_this,
-                                                     int *range_next)
+__device__ __forceinline__ void drop_commit_body(T *x, void *accv, int32_t *cnt, const int *range_this,
+                                                 int *range_next)
 {
     const int j0 = range_this[0], j1 = range_this[1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1601,6 +1658,15 @@ __global__ void __launch_bounds__(kWG) k_drop_commit(T *x, void *accv, int32_t *
             }
         }
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_drop_commit(T *x, void *accv, int32_t *cnt, const int *range_this,
+                                                     int *range_next, GateDev gt)
+{
+    if (gate_closed(gt.halt)) return;
+    drop_commit_body<T>(x, accv, cnt, range_this, range_next);
+    gate_commit_end(gt);
 }
 
 __global__ void k_reset_ranges(int *hdr)
@@ -2149,6 +2215,61 @@ int read_status(const pct_plan &pl, void *ws, int reset, uint32_t *bits, void *s
     return e;
 }
 
+static GateDev gate_dev(void *ws, const Layout &L, bool on)
+{
+    int *hdr = reinterpret_cast<int *>(wsb(ws) + L.hdr);
+    GateDev gt{};
+    if (!on) return gt;
+    gt.halt = hdr + kHdrHalt;
+    gt.wg_done = reinterpret_cast<unsigned *>(hdr + kHdrGateCount);
+    gt.cancel = hdr + kHdrCancel;
+    gt.done = reinterpret_cast<long long *>(hdr + kHdrDone);
+    gt.status = reinterpret_cast<unsigned *>(hdr + kHdrStatus);
+    return gt;
+}
+
+int write_cancel(pct_plan &pl, void *ws, int32_t request)
+{
+    hipStream_t cs = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(pl.mu);
+        if (!pl.cancel_stream) {
+            hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+            pl.cancel_stream = cs;
+        }
+        cs = static_cast<hipStream_t>(pl.cancel_stream);
+    }
+    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    int *word = reinterpret_cast<int *>(wsb(ws) + L.hdr) + kHdrCancel;
+    hipError_t e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(word), request != 0 ? 1 : 0, 1, cs);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(cs);
+}
+
+int read_progress(const pct_plan &pl, void *ws, int64_t *done, int *halted, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    int32_t h[kHdrDone + 2];
+    hipError_t e = hipMemcpyAsync(h, wsb(ws) + L.hdr, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    int64_t d;
+    std::memcpy(&d, h + kHdrDone, sizeof(d));
+    *done = d;
+    *halted = h[kHdrHalt] != 0;
+    return hipSuccess;
+}
+
+int launch_gate_reset(const pct_plan &pl, void *ws, void *stream)
+{
+    Layout L = layout_for(pl.nvox, pl.K, PCT_F32);
+    hipLaunchKernelGGL(k_gate_begin, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), gate_dev(ws, L, true));
+    return hipGetLastError();
+}
+
 int launch_trace(const pct_plan &pl, const ProtonsDev &p, int64_t first, int64_t count, int32_t max_nnz,
                  int32_t *vox, double *chord, int32_t *nnz, void *ws, void *stream)
 {
@@ -2284,7 +2405,7 @@ void profile_release(pct_plan &pl)
 template <typename T, int CHORD, bool HULL>
 static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, T *x, void *acc, int32_t *cnt,
                          int *range, const PathSrc &src, const GridDev &g, int64_t lo, int64_t hi,
-                         double lambda, unsigned *status)
+                         double lambda, unsigned *status, const int *halt)
 {
     const int64_t n = hi - lo;
     switch (lanes) {
@@ -2294,7 +2415,7 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
             const unsigned grid = unsigned((n + (64 / LPP) - 1) / (64 / LPP));                                \
             const size_t lds = size_t(64 / LPP) * kStageDoubles<HULL> * size_t(src.nvmax) * sizeof(double) + stash_bytes<T>(); \
             hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, acc, \
-                               cnt, range, src, g, lo, hi, lambda, status);                                     \
+                               cnt, range, src, g, lo, hi, lambda, status, halt);                               \
         }                                                                                                        \
         break;                                                                                                   \
     }
@@ -2305,7 +2426,7 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
 #undef PCT_LAUNCH_LPP
     default:
         hipLaunchKernelGGL((k_drop_rows<T, CHORD, HULL>), dim3(grid_for(n)), dim3(kWG), 0, s, p, b, x, acc, cnt,
-                           range, src, g, lo, hi, lambda, status);
+                           range, src, g, lo, hi, lambda, status, halt);
     }
 }
 
@@ -2364,7 +2485,7 @@ template <int CHORD, bool HULL>
 static void launch_bin(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, const float *x,
                        const BinsDev &bins, int par, unsigned long long *ovf, int *ovf_flag, const PathSrc &src,
                        const GridDev &g, int64_t lo, int64_t hi, double lambda, unsigned *status,
-                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+                       const int *halt, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     const int64_t n = hi - lo;
     switch (lanes) {
@@ -2377,10 +2498,11 @@ static void launch_bin(int lanes, hipStream_t s, const ProtonsDev &p, const floa
                                stash_bytes<float>();                                                      \
             if (ev0)                                                                                             \
                 hipExtLaunchKernelGGL((k_drop_bin<CHORD, LPP, HULL>), dim3(grid), dim3(64), uint32_t(lds), s, ev0, \
-                                      ev1, 0u, p, b, x, bins, par, ovf, ovf_flag, src, g, lo, hi, lambda, status); \
+                                      ev1, 0u, p, b, x, bins, par, ovf, ovf_flag, src, g, lo, hi, lambda, status, \
+                                      halt);                                                                     \
             else                                                                                                 \
                 hipLaunchKernelGGL((k_drop_bin<CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, bins,  \
-                                   par, ovf, ovf_flag, src, g, lo, hi, lambda, status);                         \
+                                   par, ovf, ovf_flag, src, g, lo, hi, lambda, status, halt);                   \
         }                                                                                                        \
         break;                                                                                                   \
     }
@@ -2419,6 +2541,8 @@ void graph_release(pct_plan &pl)
     pl.graph_key.clear();
     if (pl.capture_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(pl.capture_stream));
     pl.capture_stream = nullptr;
+    if (pl.cancel_stream) (void)hipStreamDestroy(static_cast<hipStream_t>(pl.cancel_stream));
+    pl.cancel_stream = nullptr;
 }
 
 // Buffers of the fused FP32 schedule: X[0] = x, X[1] in the workspace,
@@ -2560,6 +2684,8 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
     int32_t *cnt = reinterpret_cast<int32_t *>(wsb(ws) + L.cnt);
     GridDev g = grid_dev(pl.grid);
     const unsigned commit_grid = unsigned(std::min<int64_t>(4096, (pl.nvox + kWG - 1) / kWG));
+    const bool cancellable = (o.flags & PCT_DROP_CANCELLABLE) != 0;
+    const GateDev gate = gate_dev(ws, L, cancellable);
 
     // Separate schedule: re-arm the range words, then block kernel + commit
     // per block.
@@ -2573,13 +2699,15 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
             int *r_next = hdr + (seq % 2 == 0 ? kHdrRange1 : kHdrRange0);
             const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
             if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
-            launch_block<T, CHORD, HULL>(lanes, s, p, b, x, acc, cnt, r_this, src, g, lo, hi, o.lambda, status);
+            launch_block<T, CHORD, HULL>(lanes, s, p, b, x, acc, cnt, r_this, src, g, lo, hi, o.lambda, status,
+                                         gate.halt);
             if (sample) {
                 (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
                 pl.prof_used[0]++;
                 (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1]), s);
             }
-            hipLaunchKernelGGL(k_drop_commit<T>, dim3(commit_grid), dim3(kWG), 0, s, x, acc, cnt, r_this, r_next);
+            hipLaunchKernelGGL(k_drop_commit<T>, dim3(commit_grid), dim3(kWG), 0, s, x, acc, cnt, r_this, r_next,
+                               gate);
             if (sample) {
                 (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1] + 1), s);
                 pl.prof_used[1]++;
@@ -2594,7 +2722,7 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                         nslab <= win_words && o.block <= kBinMaxRows && pl.nvox < (int64_t(1) << 30) &&
                         ws_bytes >= L.total + 2 * slot_bytes(o.block) + bin_bytes(o.block, nslab);
     const bool comp = binned && !(o.flags & PCT_DROP_NO_COMPENSATION);
-    const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT) && !binned;
+    const bool fused = sizeof(T) == 4 && lanes > 1 && !(o.flags & PCT_DROP_SEPARATE_COMMIT) && !binned && !cancellable;
     // tracing ahead doubles the workgroups of a launch; with blocks above
     // kPipeMaxBlock protons the plain fused schedule is the faster one
     // (measured: 3200-proton blocks 165 vs 169 ms per sweep traced ahead, 6400-proton
@@ -2640,16 +2768,16 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
                         pl.prof_used[1]++;
                     }
                     launch_bin<CHORD, HULL>(lanes, s, p, b, reinterpret_cast<const float *>(x), bins, par, ovf,
-                                            ovf_flag + par, src, g, lo, hi, o.lambda, status, e[0], e[1]);
+                                            ovf_flag + par, src, g, lo, hi, o.lambda, status, gate.halt, e[0], e[1]);
                     if (sample)
                         hipExtLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG),
                                               uint32_t(win_lds), s, e[2], e[3], 0u, p, lo, int(hi - lo), bins, par,
                                               ovf, ovf_flag, reinterpret_cast<float *>(x), xlo, g, zc, nzc,
-                                              comp ? 1 : 0, status);
+                                              comp ? 1 : 0, status, gate);
                     else
                         hipLaunchKernelGGL(k_slab_commit, dim3(unsigned(nslab * nzc)), dim3(kSlabWG), win_lds, s, p,
                                            lo, int(hi - lo), bins, par, ovf, ovf_flag, reinterpret_cast<float *>(x),
-                                           xlo, g, zc, nzc, comp ? 1 : 0, status);
+                                           xlo, g, zc, nzc, comp ? 1 : 0, status, gate);
                 }
                 return;
             }
@@ -2716,8 +2844,10 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
         uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
         uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes),
-        uint64_t(fused) + 2 * uint64_t(pipe) + 4 * uint64_t(binned) + 8 * uint64_t(comp), bits_of(o.lambda),
+        uint64_t(fused) + 2 * uint64_t(pipe) + 4 * uint64_t(binned) + 8 * uint64_t(comp) + 16 * uint64_t(cancellable),
+        bits_of(o.lambda),
         0};
+    if (cancellable) hipLaunchKernelGGL(k_gate_begin, dim3(1), dim3(64), 0, s, gate);
     if (comp) {
         // the compensation words start at zero in every call (outside the graph)
         hipLaunchKernelGGL(k_zero_f32, dim3(unsigned(std::min<int64_t>(2048, (pl.nvox + 255) / 256))), dim3(256), 0, s,

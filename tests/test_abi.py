@@ -156,7 +156,7 @@ def test_compute_calls_validate_before_device(plan):
 
 
 @pytest.mark.parametrize("field,value", [("block", 0), ("lambda_", 0.0), ("lambda_", float("inf")), ("n_iter", -1),
-                                         ("dtype", 3), ("chord", 9), ("flags", 0x80), ("block_begin", -1),
+                                         ("dtype", 3), ("chord", 9), ("flags", 0x100), ("block_begin", -1),
                                          ("block_end", 2), ("block_begin", 3), ("lanes", 2), ("lanes", 128), ("block", 1 << 19),
                                          ("reserved", 1)])
 def test_drop_options_validated(plan, field, value):
@@ -176,10 +176,27 @@ def test_drop_options_validated(plan, field, value):
 def test_drop_valid_options_reach_workspace_check(plan):
     L = _lib.lib()
     p = fake_protons(100)
-    o = _lib.make_opts(64, 0.1, 1, 0)
-    st = L.pct_drop_iterate(plan, C.byref(p), C.c_void_p(0x5000), C.c_void_p(0x6000), C.byref(o), FAKE_WS,
-                            ws_size(plan), None)
-    assert st == -2
+    for flags in (0, _lib.PCT_DROP_CANCELLABLE, _lib.PCT_DROP_CANCELLABLE | _lib.PCT_DROP_NO_COMPENSATION):
+        o = _lib.make_opts(64, 0.1, 1, 0, flags=flags)
+        st = L.pct_drop_iterate(plan, C.byref(p), C.c_void_p(0x5000), C.c_void_p(0x6000), C.byref(o), FAKE_WS,
+                                ws_size(plan), None)
+        assert st == -2, flags
+
+
+def test_drop_cancel_and_progress_validation(plan):
+    L = _lib.lib()
+    nb = ws_size(plan)
+    done = C.c_int64(-5)
+    assert L.pct_drop_cancel(None, FAKE_WS, nb, 1) == -1
+    assert L.pct_drop_cancel(plan, None, nb, 1) == -1
+    assert L.pct_drop_cancel(plan, FAKE_WS, nb, 1) == -2        # not uploaded: nothing written
+    assert L.pct_drop_cancel(plan, FAKE_WS, 16, 0) == -2        # too small
+    assert L.pct_drop_progress(None, FAKE_WS, nb, C.byref(done), None) == -1
+    assert L.pct_drop_progress(plan, None, nb, C.byref(done), None) == -1
+    assert L.pct_drop_progress(plan, FAKE_WS, nb, None, None) == -1
+    assert L.pct_drop_progress(plan, FAKE_WS, nb, C.byref(done), None) == -2
+    assert done.value == -5
+    assert L.pct_status_string(-8) == b"stopped on a cancel request"
 
 
 def test_tv_validation(plan):
@@ -261,7 +278,7 @@ def test_stored_row_calls_validate(plan):
         o = _lib.make_opts(64, 0.1, 1, 0, chord="f16")
         setattr(o, field, value)
         assert run(plan, C.byref(rows), v, v, C.byref(o), FAKE_WS, nb, None) == -1, field
-    for field, value in (("dtype", 1), ("flags", 0x8)):
+    for field, value in (("dtype", 1), ("flags", 0x8), ("flags", _lib.PCT_DROP_CANCELLABLE)):
         o = _lib.make_opts(64, 0.1, 1, 0, chord="f16")
         setattr(o, field, value)
         assert run(plan, C.byref(rows), v, v, C.byref(o), FAKE_WS, nb, None) == -7, field
