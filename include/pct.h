@@ -237,6 +237,14 @@ typedef struct {
  * (FP64, or FP32 without the bins' workspace); the fused and traced-ahead
  * atomic schedules, whose launches commit the previous block, are not used. */
 #define PCT_DROP_CANCELLABLE 0x80u
+/* Deterministic FP64 block sums: each contribution rho_i a_ij is split into
+ * its bits above 2^-28 and the rest rounded at 2^-72, and both parts are
+ * summed in 64-bit integers (two accumulator words per voxel), so FP64 runs
+ * are bitwise reproducible whatever the order of the adds (the default FP64
+ * schedule adds doubles with atomics, whose order varies).  A contribution of
+ * 2^16 or more is clamped and raises PCT_DEV_ACC_RANGE; B must be below 2^19.
+ * FP32 block sums are integers already: the flag changes nothing there. */
+#define PCT_DROP_DETERMINISTIC 0x100u
 
 /* Workspace bytes for this plan and x of type dtype.  n > 0 adds, for DROP
  * blocks of up to n protons, two row slots (the traced-ahead schedule,

@@ -23,6 +23,7 @@ PCT_DROP_NO_TRACE_AHEAD = 0x10
 PCT_DROP_FUSED_COMMIT = 0x20
 PCT_DROP_NO_COMPENSATION = 0x40
 PCT_DROP_CANCELLABLE = 0x80
+PCT_DROP_DETERMINISTIC = 0x100
 PCT_ERR_CANCELLED = -8
 DEV_BITS = {0x1: "row_overflow", 0x2: "nonfinite", 0x4: "reentry", 0x8: "acc_range", 0x10: "bad_row",
             0x20: "cancelled"}

@@ -437,10 +437,11 @@ int pct_drop_iterate(const pct_plan *plan, const pct_protons *p, const float *b,
     if (o->chord < PCT_CHORD_F64 || o->chord > PCT_CHORD_BF16) return PCT_ERR_INVALID_ARG;
     if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT |
                      PCT_DROP_NO_TRACE_AHEAD | PCT_DROP_FUSED_COMMIT | PCT_DROP_NO_COMPENSATION |
-                     PCT_DROP_CANCELLABLE))
+                     PCT_DROP_CANCELLABLE | PCT_DROP_DETERMINISTIC))
         return PCT_ERR_INVALID_ARG;
     if (o->block > (int64_t(1) << 31)) return PCT_ERR_INVALID_ARG;
-    if (o->dtype == PCT_F32 && o->block >= (int64_t(1) << 19)) return PCT_ERR_INVALID_ARG;
+    if ((o->dtype == PCT_F32 || (o->flags & PCT_DROP_DETERMINISTIC)) && o->block >= (int64_t(1) << 19))
+        return PCT_ERR_INVALID_ARG;
     if (o->lanes != 0 && o->lanes != 1 && o->lanes != 8 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64)
         return PCT_ERR_INVALID_ARG;
     if (o->reserved != 0) return PCT_ERR_INVALID_ARG;
@@ -531,7 +532,7 @@ int pct_drop_iterate_rows(const pct_plan *plan, const pct_rows *rows, const floa
     if (o->block <= 0 || !finite_pos(o->lambda) || o->n_iter < 0 || !valid_dtype(o->dtype)) return PCT_ERR_INVALID_ARG;
     if (o->chord != rows->chord_type) return PCT_ERR_INVALID_ARG;
     if (o->flags & ~(PCT_DROP_CHECK_FINITE | PCT_DROP_NO_GRAPH | PCT_DROP_PROFILE | PCT_DROP_SEPARATE_COMMIT |
-                     PCT_DROP_CANCELLABLE))
+                     PCT_DROP_CANCELLABLE | PCT_DROP_DETERMINISTIC))
         return PCT_ERR_INVALID_ARG;
     if (o->block >= (int64_t(1) << 19)) return PCT_ERR_INVALID_ARG;
     if (o->lanes != 0 && o->lanes != 16 && o->lanes != 32 && o->lanes != 64) return PCT_ERR_INVALID_ARG;

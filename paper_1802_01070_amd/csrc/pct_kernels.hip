@@ -272,11 +272,58 @@ __device__ __forceinline__ void unpack_accumulator(unsigned long long w, int &cn
     sum = double(V) * (1.0 / kFixScale);
 }
 
+// Order-independent FP64 block sums (deterministic mode): each contribution
+// v is split into hi = round(v 2^28) and lo = round((v - hi 2^-28) 2^72), the
+// first part exact (v's bits above 2^-28), the second within 2^-73, and both
+// are summed in 64-bit integers, so the block sum hi 2^-28 + lo 2^-72 does not
+// depend on the order of the adds.  A contribution of 2^16 or more (NaN: 0)
+// is clamped and raises PCT_DEV_ACC_RANGE, which keeps the sums of blocks
+// below 2^19 rows inside 64 bits.
+constexpr double kDetHiScale = 268435456.0;                 // 2^28
+constexpr double kDetLoScale = 4722366482869645213696.0;    // 2^72
+constexpr double kDetMax = 65536.0;                         // 2^16
+
+__device__ __forceinline__ void det_add(long long *hi, long long *lo, int j, double v, unsigned *status)
+{
+    if (!(fabs(v) < kDetMax)) {
+        atomicOr(status, PCT_DEV_ACC_RANGE);
+        v = v != v ? 0.0 : fmin(fmax(v, -kDetMax), kDetMax);
+    }
+    const double qh = rint(v * kDetHiScale);
+    const double r = v - qh * (1.0 / kDetHiScale);
+    atomicAdd(reinterpret_cast<unsigned long long *>(hi) + j, static_cast<unsigned long long>(static_cast<long long>(qh)));
+    atomicAdd(reinterpret_cast<unsigned long long *>(lo) + j, static_cast<unsigned long long>(llrint(r * kDetLoScale)));
+}
+
+__device__ __forceinline__ double det_sum(long long hi, long long lo)
+{
+    return double(hi) * (1.0 / kDetHiScale) + double(lo) * (1.0 / kDetLoScale);
+}
+
+// One piece of a row into the block's accumulation: FP32 packed word; FP64
+// double atomic, or the integer pair when acc_lo is given; the row count once.
+template <typename T>
+__device__ __forceinline__ void scatter_one(void *acc, long long *acc_lo, int32_t *cnt, int j, double v, bool first,
+                                            unsigned *status)
+{
+    if constexpr (sizeof(T) == 4) {
+        atomicAdd(static_cast<unsigned long long *>(acc) + j, pack_contribution(v, first, status));
+    } else {
+        if (acc_lo)
+            det_add(static_cast<long long *>(acc), acc_lo, j, v, status);
+        else
+            atomicAdd(static_cast<double *>(acc) + j, v);
+        if (first) atomicAdd(cnt + j, 1);
+    }
+}
+
 // Scatter of one row: acc_j += rho a_ij and s_j += 1 once per row.  FP32 value
-// type: packed 64-bit accumulator; FP64: double accumulator plus int count.
+// type: packed 64-bit accumulator; FP64: double accumulator (or the integer
+// pair) plus int count.
 template <typename T>
 struct DropScatterSink {
     void *acc;
+    long long *acc_lo = nullptr;  // FP64 deterministic mode: low words of the integer pair
     int32_t *cnt;
     unsigned *status;
     Reentry re;
@@ -287,12 +334,7 @@ struct DropScatterSink {
     {
         bool first;
         re.visit(j, ix, iy, iz, c, first);
-        if constexpr (sizeof(T) == 4) {
-            atomicAdd(static_cast<unsigned long long *>(acc) + j, pack_contribution(rho * c, first, status));
-        } else {
-            atomicAdd(static_cast<double *>(acc) + j, rho * c);
-            if (first) atomicAdd(cnt + j, 1);
-        }
+        scatter_one<T>(acc, acc_lo, cnt, j, rho * c, first, status);
         jmin = min(jmin, j);
         jmax = max(jmax, j);
     }
@@ -334,7 +376,8 @@ template <typename T, int CHORD, bool HULL>
 __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__restrict__ b,
                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
                                                    const PathSrc src,  GridDev g, int64_t lo,
-                                                   int64_t hi, double lambda, unsigned *status, const int *halt)
+                                                   int64_t hi, double lambda, unsigned *status, long long *acc_lo,
+                                                   const int *halt)
 {
     if (gate_closed(halt)) return;
     int64_t i = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -366,6 +409,7 @@ __global__ void __launch_bounds__(kWG) k_drop_rows(ProtonsDev p, const float *__
         if (s.re.unsafe) raise_status(status, PCT_DEV_REENTRY);
         if (s.n2 > 0.0) {
             sc.acc = acc;
+            sc.acc_lo = acc_lo;
             sc.cnt = cnt;
             sc.status = status;
             sc.rho = lambda * (bi - s.dot) / s.n2;
@@ -684,7 +728,8 @@ template <typename T, int CHORD, int LPP, bool HULL>
 __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__restrict__ b,
                                                    const T *__restrict__ x, void *acc, int32_t *cnt, int *range,
                                                    const PathSrc src,  GridDev g, int64_t lo,
-                                                   int64_t hi, double lambda, unsigned *status, const int *halt)
+                                                   int64_t hi, double lambda, unsigned *status, long long *acc_lo,
+                                                   const int *halt)
 {
     if (gate_closed(halt)) return;
     using CT = typename std::conditional<sizeof(T) == 4, float, double>::type;
@@ -753,18 +798,14 @@ __global__ void __launch_bounds__(64) k_drop_block(ProtonsDev p, const float *__
                 const int j = e & 0x7FFFFFFF;
                 const bool first = e < 0;
                 const double v = rho * double(sc[q * 64 + lane]);
-                if constexpr (sizeof(T) == 4) {
-                    atomicAdd(static_cast<unsigned long long *>(acc) + j, pack_contribution(v, first, status));
-                } else {
-                    atomicAdd(static_cast<double *>(acc) + j, v);
-                    if (first) atomicAdd(cnt + j, 1);
-                }
+                scatter_one<T>(acc, acc_lo, cnt, j, v, first, status);
                 jmin = min(jmin, j);
                 jmax = max(jmax, j);
             }
         } else {
             DropScatterSink<T> sc2;
             sc2.acc = acc;
+            sc2.acc_lo = acc_lo;
             sc2.cnt = cnt;
             sc2.status = status;
             sc2.rho = rho;
@@ -1617,7 +1658,7 @@ __global__ void __launch_bounds__(kSlabWG) k_slab_commit(ProtonsDev p, int64_t l
 // Also re-arms the range words of the next block.
 template <typename T>
 __device__ __forceinline__ void drop_commit_body(T *x, void *accv, int32_t *cnt, const int *range_this,
-                                                 int *range_next)
+                                                 int *range_next, long long *acc_lo)
 {
     const int j0 = range_this[0], j1 = range_this[1];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1649,11 +1690,18 @@ __device__ __forceinline__ void drop_commit_body(T *x, void *accv, int32_t *cnt,
     }
     for (int j = j0 + int(blockIdx.x * blockDim.x + threadIdx.x); j <= j1; j += stride) {
         {
-            double *acc = static_cast<double *>(accv);
             const int c = cnt[j];
             if (c != 0) {
-                x[j] = T(double(x[j]) + acc[j] / double(c));
-                acc[j] = 0.0;
+                if (acc_lo) {
+                    long long *hi = static_cast<long long *>(accv);
+                    x[j] = T(double(x[j]) + det_sum(hi[j], acc_lo[j]) / double(c));
+                    hi[j] = 0;
+                    acc_lo[j] = 0;
+                } else {
+                    double *acc = static_cast<double *>(accv);
+                    x[j] = T(double(x[j]) + acc[j] / double(c));
+                    acc[j] = 0.0;
+                }
                 cnt[j] = 0;
             }
         }
@@ -1662,10 +1710,10 @@ __device__ __forceinline__ void drop_commit_body(T *x, void *accv, int32_t *cnt,
 
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_drop_commit(T *x, void *accv, int32_t *cnt, const int *range_this,
-                                                     int *range_next, GateDev gt)
+                                                     int *range_next, long long *acc_lo, GateDev gt)
 {
     if (gate_closed(gt.halt)) return;
-    drop_commit_body<T>(x, accv, cnt, range_this, range_next);
+    drop_commit_body<T>(x, accv, cnt, range_this, range_next, acc_lo);
     gate_commit_end(gt);
 }
 
@@ -2405,7 +2453,7 @@ void profile_release(pct_plan &pl)
 template <typename T, int CHORD, bool HULL>
 static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const float *b, T *x, void *acc, int32_t *cnt,
                          int *range, const PathSrc &src, const GridDev &g, int64_t lo, int64_t hi,
-                         double lambda, unsigned *status, const int *halt)
+                         double lambda, unsigned *status, long long *acc_lo, const int *halt)
 {
     const int64_t n = hi - lo;
     switch (lanes) {
@@ -2415,7 +2463,7 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
             const unsigned grid = unsigned((n + (64 / LPP) - 1) / (64 / LPP));                                \
             const size_t lds = size_t(64 / LPP) * kStageDoubles<HULL> * size_t(src.nvmax) * sizeof(double) + stash_bytes<T>(); \
             hipLaunchKernelGGL((k_drop_block<T, CHORD, LPP, HULL>), dim3(grid), dim3(64), lds, s, p, b, x, acc, \
-                               cnt, range, src, g, lo, hi, lambda, status, halt);                               \
+                               cnt, range, src, g, lo, hi, lambda, status, acc_lo, halt);                       \
         }                                                                                                        \
         break;                                                                                                   \
     }
@@ -2426,7 +2474,7 @@ static void launch_block(int lanes, hipStream_t s, const ProtonsDev &p, const fl
 #undef PCT_LAUNCH_LPP
     default:
         hipLaunchKernelGGL((k_drop_rows<T, CHORD, HULL>), dim3(grid_for(n)), dim3(kWG), 0, s, p, b, x, acc, cnt,
-                           range, src, g, lo, hi, lambda, status, halt);
+                           range, src, g, lo, hi, lambda, status, acc_lo, halt);
     }
 }
 
@@ -2686,6 +2734,9 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
     const unsigned commit_grid = unsigned(std::min<int64_t>(4096, (pl.nvox + kWG - 1) / kWG));
     const bool cancellable = (o.flags & PCT_DROP_CANCELLABLE) != 0;
     const GateDev gate = gate_dev(ws, L, cancellable);
+    // FP64 deterministic mode: integer block sums in the first two accumulators
+    const bool det = sizeof(T) == 8 && (o.flags & PCT_DROP_DETERMINISTIC) != 0;
+    long long *acc_lo = det ? reinterpret_cast<long long *>(wsb(ws) + L.acc + L.acc_stride) : nullptr;
 
     // Separate schedule: re-arm the range words, then block kernel + commit
     // per block.
@@ -2700,14 +2751,14 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
             const bool sample = record_events && (seq % every == 0) && pl.prof_used[0] < kProfSamples;
             if (sample) (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0]), s);
             launch_block<T, CHORD, HULL>(lanes, s, p, b, x, acc, cnt, r_this, src, g, lo, hi, o.lambda, status,
-                                         gate.halt);
+                                         acc_lo, gate.halt);
             if (sample) {
                 (void)hipEventRecord(prof_event(pl, 0, 2 * pl.prof_used[0] + 1), s);
                 pl.prof_used[0]++;
                 (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1]), s);
             }
             hipLaunchKernelGGL(k_drop_commit<T>, dim3(commit_grid), dim3(kWG), 0, s, x, acc, cnt, r_this, r_next,
-                               gate);
+                               acc_lo, gate);
             if (sample) {
                 (void)hipEventRecord(prof_event(pl, 1, 2 * pl.prof_used[1] + 1), s);
                 pl.prof_used[1]++;
@@ -2844,7 +2895,8 @@ static int drop_loop(pct_plan &pl, const ProtonsDev &p, int64_t n, const float *
         reinterpret_cast<uint64_t>(x),        reinterpret_cast<uint64_t>(ws),
         uint64_t(n), uint64_t(o.block), uint64_t(o.block_begin), uint64_t(o.block_end),
         uint64_t(o.dtype), uint64_t(CHORD), uint64_t(lanes),
-        uint64_t(fused) + 2 * uint64_t(pipe) + 4 * uint64_t(binned) + 8 * uint64_t(comp) + 16 * uint64_t(cancellable),
+        uint64_t(fused) + 2 * uint64_t(pipe) + 4 * uint64_t(binned) + 8 * uint64_t(comp) + 16 * uint64_t(cancellable) +
+            32 * uint64_t(det),
         bits_of(o.lambda),
         0};
     if (cancellable) hipLaunchKernelGGL(k_gate_begin, dim3(1), dim3(64), 0, s, gate);

@@ -156,7 +156,7 @@ def test_compute_calls_validate_before_device(plan):
 
 
 @pytest.mark.parametrize("field,value", [("block", 0), ("lambda_", 0.0), ("lambda_", float("inf")), ("n_iter", -1),
-                                         ("dtype", 3), ("chord", 9), ("flags", 0x100), ("block_begin", -1),
+                                         ("dtype", 3), ("chord", 9), ("flags", 0x200), ("block_begin", -1),
                                          ("block_end", 2), ("block_begin", 3), ("lanes", 2), ("lanes", 128), ("block", 1 << 19),
                                          ("reserved", 1)])
 def test_drop_options_validated(plan, field, value):
@@ -176,11 +176,24 @@ def test_drop_options_validated(plan, field, value):
 def test_drop_valid_options_reach_workspace_check(plan):
     L = _lib.lib()
     p = fake_protons(100)
-    for flags in (0, _lib.PCT_DROP_CANCELLABLE, _lib.PCT_DROP_CANCELLABLE | _lib.PCT_DROP_NO_COMPENSATION):
-        o = _lib.make_opts(64, 0.1, 1, 0, flags=flags)
+    for flags in (0, _lib.PCT_DROP_CANCELLABLE, _lib.PCT_DROP_CANCELLABLE | _lib.PCT_DROP_NO_COMPENSATION,
+                  _lib.PCT_DROP_DETERMINISTIC):
+        for dtype in (0, 1):
+            o = _lib.make_opts(64, 0.1, 1, dtype, flags=flags)
+            st = L.pct_drop_iterate(plan, C.byref(p), C.c_void_p(0x5000), C.c_void_p(0x6000), C.byref(o), FAKE_WS,
+                                    ws_size(plan), None)
+            assert st == -2, (flags, dtype)
+
+
+def test_deterministic_fp64_limits_the_block(plan):
+    # the integer block sums hold blocks below 2^19 rows (FP64 otherwise allows 2^31)
+    L = _lib.lib()
+    p = fake_protons(1 << 20)
+    for flags, want in ((0, -2), (_lib.PCT_DROP_DETERMINISTIC, -1)):
+        o = _lib.make_opts(1 << 19, 0.1, 1, 1, flags=flags)
         st = L.pct_drop_iterate(plan, C.byref(p), C.c_void_p(0x5000), C.c_void_p(0x6000), C.byref(o), FAKE_WS,
                                 ws_size(plan), None)
-        assert st == -2, flags
+        assert st == want, flags
 
 
 def test_drop_cancel_and_progress_validation(plan):

@@ -122,7 +122,7 @@ def test_calls_without_the_flag_ignore_a_request():
 
 
 @pytest.mark.parametrize("dtype,flags", [(torch.float32, PCT_DROP_NO_COMPENSATION), (torch.float32, 0),
-                                         (torch.float64, 0)])
+                                         (torch.float64, 0), (torch.float64, _lib.PCT_DROP_DETERMINISTIC)])
 def test_cancel_mid_run_then_resume(dtype, flags):
     m = 10_000_000 if dtype == torch.float32 else 2_000_000
     sc, plan, pr, b = setup(m)
@@ -152,7 +152,7 @@ def test_cancel_mid_run_then_resume(dtype, flags):
     if n_iter - s > 0:
         api.pct_drop_iterate(plan, pr, b, x, block=CFG.block, lam=CFG.lam, n_iter=n_iter - s, flags=flags)
     torch.cuda.synchronize()
-    if dtype == torch.float32 and flags & PCT_DROP_NO_COMPENSATION:
+    if (dtype == torch.float32 and flags & PCT_DROP_NO_COMPENSATION) or flags & _lib.PCT_DROP_DETERMINISTIC:
         assert torch.equal(x, ref)
     elif dtype == torch.float32:
         # compensated: each call starts its compensation word at zero, so the
