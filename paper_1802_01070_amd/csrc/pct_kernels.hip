@@ -52,9 +52,10 @@ __device__ __forceinline__ bool gate_closed(const int *halt) { return halt && *h
 __device__ __forceinline__ void gate_commit_end(const GateDev &gt)
 {
     if (!gt.halt) return;
+    // every wave of the workgroup has read the gate (a load consumed by the
+    // entry branch) before the workgroup is counted
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         const unsigned k = atomicAdd(gt.wg_done, 1u);
         if (k == gridDim.x - 1) {
             *gt.wg_done = 0u;
