@@ -57,9 +57,11 @@ GridDev grid_dev(const pct_grid &g)
         d.n[a] = n[a];
         d.pitch[a] = g.pitch[a];
         d.inv_pitch[a] = 1.0 / g.pitch[a];
+        d.inv_n[a] = 1.0 / double(n[a]);
         d.lo[a] = g.origin[a];
         d.hi[a] = g.origin[a] + n[a] * g.pitch[a];
     }
+    d.inv_nxy = 1.0 / (double(n[0]) * double(n[1]));
     return d;
 }
 

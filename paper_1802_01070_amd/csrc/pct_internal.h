@@ -20,6 +20,8 @@ struct GridDev {
     int32_t n[3];
     double pitch[3];
     double inv_pitch[3];
+    double inv_n[3];   // 1 / n and 1 / (nx ny): exact integer quotients by the extents
+    double inv_nxy;
     double lo[3];  // origin
     double hi[3];  // origin + n*pitch
 };

@@ -1261,12 +1261,14 @@ struct BinsDev {
 };
 constexpr unsigned kEmptyBin = 0xFFFFFFFFu;
 
-// Dominant in-plane axis of the block: the walk's test on its first record.
+// Dominant in-plane axis of the block, from its first record's gantry angle.
+// It only routes pieces (rows of the other axis go to the overflow words,
+// whose integer sums are the same), so a single-precision hardware cosine
+// serves, the same in every kernel of the block.
 __device__ __forceinline__ int block_axis(const ProtonsDev &p, int64_t lo)
 {
-    double sn, cs;
-    sincos(double(p.gantry[lo]), &sn, &cs);
-    return fabs(cs) >= fabs(sn) ? 0 : 1;
+    const float c = __cosf(p.gantry[lo]);
+    return c * c >= 0.5f ? 0 : 1;
 }
 
 // Exact quotient floor(j / d) for j < 2^31 and 1 <= d < 2^30, from an FP64
@@ -1433,7 +1435,7 @@ k_drop_bin(ProtonsDev p, const float *__restrict__ b, const float *__restrict__ 
         const double rho = lambda * (bi - dot) / n2;
         const int axis = block_axis(p, lo);
         BinWriter bw{bins,     par, axis, g.n[0], g.n[1], int(i - lo), gp.full || gp.dom != axis, ovf, ovf_flag, -1,
-                     0,        0ull, 0u,  1.0 / double(g.n[0]), 1.0 / double(g.n[1])};
+                     0,        0ull, 0u,  g.inv_n[0], g.inv_n[1]};
         if (!spill) {
             for (int q = 0; q < ns; ++q) {
                 const int e = sj[q * 64 + lane];
@@ -1543,7 +1545,7 @@ __device__ __forceinline__ void slab_commit_body(const ProtonsDev &p, int64_t lo
     const unsigned *j1 = bins.j1 + size_t(s) * (kBinCap - 1) * bins.cap;
     const int cap = bins.cap;
     const unsigned nx = unsigned(g.n[0]), nxy = unsigned(g.n[0]) * unsigned(g.n[1]);
-    const double inv_nx = 1.0 / double(nx), inv_nxy = 1.0 / double(nxy);
+    const double inv_nx = g.inv_n[0], inv_nxy = g.inv_nxy;
     unsigned jr[kRowsPerThread];
     unsigned long long wr[kRowsPerThread];
 #pragma unroll
@@ -1587,7 +1589,7 @@ __device__ __forceinline__ void slab_commit_body(const ProtonsDev &p, int64_t lo
     }
     const bool of = ovf_flag[par] != 0;
     __syncthreads();
-    const double inv_nlat = 1.0 / double(nlat);
+    const double inv_nlat = g.inv_n[1 - axis];
     for (int q0 = 0; q0 < nw; q0 += kCommitCells * kSlabWG) {
         int jv[kCommitCells];
         unsigned long long wv[kCommitCells];
