@@ -65,7 +65,8 @@ def close(a, b, dtype, flags):
 
 SCHEDULES = [(torch.float32, 0), (torch.float32, PCT_DROP_NO_COMPENSATION),
              (torch.float32, PCT_DROP_SEPARATE_COMMIT), (torch.float64, 0),
-             (torch.float32, PCT_DROP_NO_COMPENSATION | PCT_DROP_NO_GRAPH)]
+             (torch.float32, PCT_DROP_NO_COMPENSATION | PCT_DROP_NO_GRAPH),
+             (torch.float32, PCT_DROP_NO_COMPENSATION | _lib.PCT_DROP_PROFILE)]
 
 
 @pytest.mark.parametrize("dtype,flags", SCHEDULES)
@@ -161,3 +162,24 @@ def test_cancel_mid_run_then_resume(dtype, flags):
         assert d <= 2.0 ** -22 * max(1.0, ref.abs().max().item()), d
     else:
         assert close(x, ref, dtype, flags)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_hull_paths_stop_at_a_block_boundary(dtype):
+    # per-proton hull paths run their own kernel instances; the gate is the same
+    sc, plan, pr, b = setup(20000)
+    plan.set_hull(sc.cfg.r_hull - 8.0)
+    x0 = x_start(sc, dtype)
+    flags = PCT_DROP_NO_COMPENSATION if dtype == torch.float32 else _lib.PCT_DROP_DETERMINISTIC
+    api.pct_drop_cancel(plan, True)
+    try:
+        x = run(plan, pr, b, x0, flags | PCT_DROP_CANCELLABLE, n_iter=2)
+        assert api.pct_drop_progress(plan) == (1, True)
+    finally:
+        api.pct_drop_cancel(plan, False)
+    ref = run(plan, pr, b, x0, flags, block_end=1)
+    assert torch.equal(x, ref)
+    # and resumed: the rest of the first sweep and one more
+    x = run(plan, pr, b, x, flags, block_begin=1)
+    x = run(plan, pr, b, x, flags)
+    assert torch.equal(x, run(plan, pr, b, x0, flags, n_iter=2))
