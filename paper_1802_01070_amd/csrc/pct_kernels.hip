@@ -2,7 +2,7 @@
 //
 //   k_trace        ordered emission list of each proton's path (debug/parity)
 //   k_forward      y = A x, ||a_i||^2   (one lane per proton, gathers)
-//   k_backproject  g += A^T r           (one lane per proton, atomics)
+//   k_backproject  g += A^T r           (one lane per proton, LDS-summed, atomics)
 //   k_drop_block   DROP block, LPP lanes per proton: walk -> a_i.x, ||a_i||^2 ->
 //                  rho_i -> re-walk and scatter rho_i a_ij into the block
 //                  accumulator and the per-voxel row count; records the
@@ -206,12 +206,50 @@ __global__ void __launch_bounds__(kWG) k_forward(ProtonsDev p, int64_t first, in
 // ---------------------------------------------------------------------------
 // back projection
 // ---------------------------------------------------------------------------
+// Back projection g += A^T r, one lane per proton.  The 256 rows of a
+// workgroup are consecutive in the scan, and an angle-sorted scan's
+// consecutive rows cross nearly the same voxels, so the workgroup first sums
+// its pieces in an LDS table keyed by voxel (open addressing, a few probes)
+// and each distinct voxel then reaches HBM with one atomic.  A piece that
+// finds no slot goes straight to HBM, and so do the later pieces of its lane
+// (the table is filling up: an unsorted scan).
 template <typename T>
-struct ScatterSink {
+struct BpTable {
+    static constexpr int kSlots = sizeof(T) == 4 ? 8192 : 4096;  // 64 KB / 48 KB of LDS
+    static constexpr int kBits = sizeof(T) == 4 ? 13 : 12;
+    static constexpr int kProbes = 8;
+};
+
+template <typename T>
+struct HashScatterSink {
+    int *keys;
+    T *vals;
     T *g;
     double r;
+    bool full;  // a probe sequence of this lane found no slot
     __device__ __forceinline__ void segment(double, double) {}
-    __device__ __forceinline__ void final(int j, int, int, int, double c) { atomicAdd(g + j, T(r * c)); }
+    __device__ __forceinline__ void final(int j, int, int, int, double c)
+    {
+        using B = BpTable<T>;
+        const T v = T(r * c);
+        if (!full) {
+            unsigned s = (unsigned(j) * 2654435761u) >> (32 - B::kBits);
+            for (int q = 0; q < B::kProbes; ++q) {
+                int k = *reinterpret_cast<volatile int *>(keys + s);
+                if (k == -1) {
+                    const int old = atomicCAS(keys + s, -1, j);
+                    k = old == -1 ? j : old;
+                }
+                if (k == j) {
+                    atomicAdd(vals + s, v);
+                    return;
+                }
+                s = (s + 1) & (B::kSlots - 1);
+            }
+            full = true;
+        }
+        atomicAdd(g + j, v);
+    }
 };
 
 template <typename T, bool HULL>
@@ -219,19 +257,41 @@ __global__ void __launch_bounds__(kWG) k_backproject(ProtonsDev p, int64_t first
                                                      const T *__restrict__ rv, T *gout, const PathSrc src, GridDev g,
                                                      unsigned *status)
 {
-    int64_t i = first + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double ri = double(rv[i]);
-    if (ri == 0.0) return;
-    Rec r = load_rec(p, i);
-    if (!rec_finite(r) || !isfinite(ri)) {
-        raise_status(status, PCT_DEV_NONFINITE);
-        return;
+    using B = BpTable<T>;
+    __shared__ int keys[B::kSlots];
+    __shared__ T vals[B::kSlots];
+    for (int q = threadIdx.x; q < B::kSlots; q += kWG) {
+        keys[q] = -1;
+        vals[q] = T(0);
     }
-    ScatterSink<T> s{gout, ri};
-    Merge<ScatterSink<T>, PCT_CHORD_F64> m(s, g);
-    walk_path<HULL>(r, src, g, m);
-    m.finish();
+    __syncthreads();
+    const int64_t i = first + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool active = i < n;
+    double ri = 0.0;
+    Rec r{};
+    if (active) {
+        ri = double(rv[i]);
+        if (ri == 0.0) {
+            active = false;
+        } else {
+            r = load_rec(p, i);
+            if (!rec_finite(r) || !isfinite(ri)) {
+                raise_status(status, PCT_DEV_NONFINITE);
+                active = false;
+            }
+        }
+    }
+    if (active) {
+        HashScatterSink<T> s{keys, vals, gout, ri, false};
+        Merge<HashScatterSink<T>, PCT_CHORD_F64> m(s, g);
+        walk_path<HULL>(r, src, g, m);
+        m.finish();
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < B::kSlots; q += kWG) {
+        const int k = keys[q];
+        if (k >= 0) atomicAdd(gout + k, vals[q]);
+    }
 }
 
 // ---------------------------------------------------------------------------
