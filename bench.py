@@ -345,12 +345,12 @@ def run_gradient(args):
         f"loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     sum_nnz = count_nonzeros(api, plan, pr)
     # dominant kernel: k_backproject (one lane per proton: 9 record fields and
-    # r_i in, 40 B; one FP32 atomic per nonzero)
+    # r_i in, 40 B; pieces pre-summed per workgroup in LDS, one FP32 atomic per distinct voxel)
     bp_bytes = BYTES_PER_PROTON * m + 4.0 * sum_nnz
     bp_gbs = bp_bytes / (b_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": bp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bp_gbs / HBM_PEAK_GBS,
             "traffic": None, "traffic_source": "no counter run on this workload",
-            "kernel": "k_backproject (A^T r: MLP trace per proton, one FP32 atomic per nonzero)",
+            "kernel": "k_backproject (A^T r: MLP trace per proton, pieces pre-summed per workgroup in LDS, one FP32 atomic per distinct voxel)",
             "kernel_avg_us": b_ms * 1e3, "kernel_avg_us_how": "HIP events on the stream, mean of 3 launches",
             "algorithmic_bytes_per_launch": bp_bytes, "nonzeros_per_proton": sum_nnz / m,
             "forward_kernel_avg_us": f_ms * 1e3,
