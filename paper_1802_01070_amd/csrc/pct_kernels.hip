@@ -1547,15 +1547,23 @@ constexpr int kRowsPerThread = 8;   // rows of a block per slab-commit thread
 constexpr int kCommitCells = 16;    // window cells per thread and pass of the commit
 
 // Window cell of voxel j in the slab's z range [z0, z1), or -1.
-__device__ __forceinline__ int window_cell(unsigned j, int axis, int nlat, int z0, int z1, unsigned nx, unsigned nxy,
-                                          double inv_nx, double inv_nxy)
+// Window cell of voxel j of slab s in the slab's z range [z0, z1), or -1.
+// Every entry of slab s's bins lies in slab s, so along x (axis 0)
+// j - s = nx (iy + ny iz) exactly and the cell iy + ny (iz - z0) is that
+// quotient less ny z0 (an exact FP64 quotient, rounded); along y (axis 1)
+// j - nx s = ix + nx ny iz and one exact integer division splits it.
+__device__ __forceinline__ int window_cell(unsigned j, int axis, int s, int nlat, int z0, int z1, unsigned nx,
+                                          unsigned nxy, double inv_nx, double inv_nxy)
 {
-    const unsigned iz = udiv_exact(j, nxy, inv_nxy);
-    const unsigned rr = j - iz * nxy;
-    const unsigned iy = udiv_exact(rr, nx, inv_nx);
-    const unsigned ix = rr - iy * nx;
-    const int zz = int(iz) - z0;
-    return zz >= 0 && int(iz) < z1 ? int(axis == 0 ? iy : ix) + nlat * zz : -1;
+    int cell;
+    if (axis == 0) {
+        cell = int(rint(double(j - unsigned(s)) * inv_nx)) - nlat * z0;
+    } else {
+        const unsigned rr = j - nx * unsigned(s);
+        const unsigned iz = udiv_exact(rr, nxy, inv_nxy);
+        cell = int(rr - iz * nxy) + nlat * (int(iz) - z0);
+    }
+    return cell >= 0 && cell < nlat * (z1 - z0) ? cell : -1;
 }
 
 __device__ __forceinline__ void window_add(unsigned long long *win, int cell, unsigned long long w)
@@ -1618,34 +1626,32 @@ __device__ __forceinline__ void slab_commit_body(const ProtonsDev &p, int64_t lo
             wr[m] = w[r];
         }
     }
-    // second entries of the rows with two or more (one batch of loads)
-    unsigned jb[kRowsPerThread];
-    unsigned long long wb[kRowsPerThread];
+    // the further entries of the rows with two or more (one batch of loads)
+    unsigned jb[kRowsPerThread][kBinCap - 1];
+    unsigned long long wb[kRowsPerThread][kBinCap - 1];
 #pragma unroll
     for (int m = 0; m < kRowsPerThread; ++m) {
         const int r = tid + m * kSlabWG;
-        jb[m] = kEmptyBin;
-        wb[m] = 0ull;
-        if (jr[m] != kEmptyBin && (jr[m] >> 30) >= 1u) {
-            jb[m] = j1[r];
-            wb[m] = w[cap + r];
+#pragma unroll
+        for (int k = 1; k < kBinCap; ++k) {
+            jb[m][k - 1] = kEmptyBin;
+            wb[m][k - 1] = 0ull;
+            if (jr[m] != kEmptyBin && (jr[m] >> 30) >= unsigned(k)) {
+                jb[m][k - 1] = j1[size_t(k - 1) * cap + r];
+                wb[m][k - 1] = w[size_t(k) * cap + r];
+            }
         }
     }
 #pragma unroll
     for (int m = 0; m < kRowsPerThread; ++m) {
         if (jr[m] == kEmptyBin) continue;
         const int c = int(jr[m] >> 30) + 1;
-        window_add(win,
-                   window_cell(jr[m] & 0x3FFFFFFFu, axis, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy), wr[m]);
-        if (c >= 2)
-            window_add(win, window_cell(jb[m], axis, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy),
-                       wb[m]);
-        for (int k = 2; k < c; ++k) {
-            const int r = tid + m * kSlabWG;
-            window_add(win,
-                       window_cell(j1[size_t(k - 1) * cap + r], axis, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy),
-                       w[size_t(k) * cap + r]);
-        }
+        window_add(win, window_cell(jr[m] & 0x3FFFFFFFu, axis, s, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy), wr[m]);
+#pragma unroll
+        for (int k = 1; k < kBinCap; ++k)
+            if (k < c)
+                window_add(win, window_cell(jb[m][k - 1], axis, s, nlat, z0, z1, nx, nxy, inv_nx, inv_nxy),
+                           wb[m][k - 1]);
     }
     const bool of = ovf_flag[par] != 0;
     __syncthreads();
