@@ -1606,8 +1606,6 @@ __device__ __forceinline__ void slab_commit_body(const ProtonsDev &p, int64_t lo
     const int z0 = zi * zc, z1 = min(g.n[2], z0 + zc);
     if (z0 >= z1) return;
     const int nw = nlat * (z1 - z0);
-    for (int q = tid; q < nw; q += kSlabWG) win[q] = 0ull;
-    __syncthreads();
     const unsigned *j0 = bins.j0 + (size_t(par) * bins.nslab + s) * bins.cap;
     const unsigned long long *w = bins.w + size_t(s) * kBinCap * bins.cap;
     const unsigned *j1 = bins.j1 + size_t(s) * (kBinCap - 1) * bins.cap;
@@ -1642,6 +1640,9 @@ __device__ __forceinline__ void slab_commit_body(const ProtonsDev &p, int64_t lo
             }
         }
     }
+    // the window is cleared while the entries are in flight
+    for (int q = tid; q < nw; q += kSlabWG) win[q] = 0ull;
+    __syncthreads();
 #pragma unroll
     for (int m = 0; m < kRowsPerThread; ++m) {
         if (jr[m] == kEmptyBin) continue;
