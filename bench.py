@@ -162,7 +162,7 @@ def sweep_roofline(ms_per_sweep, T, m, sum_nnz, kernel):
     nbytes = (BYTES_PER_PROTON * m + BYTES_PER_NONZERO * sum_nnz) / T
     gbs = nbytes / (k_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None, "traffic_source": "counters taken on the FP32-chord 10^7-proton run only",
+            "traffic": None, "traffic_source": "counters taken on the FP32 head-scan headline run only",
             "kernel": kernel, "kernel_avg_us": k_ms * 1e3,
             "kernel_avg_us_how": "sweeps timed with HIP events on the sweep's stream / block launches",
             "algorithmic_bytes_per_launch": nbytes}
@@ -272,7 +272,8 @@ def run_precision(args):
     sum_nnz = count_nonzeros(api, plan, pr)
     T = (m + cfg.block - 1) // cfg.block
     roof = sweep_roofline(f16_ms / n_iter, T, m, sum_nnz,
-                          "k_drop_pipe with FP16 chords (trace ahead, DROP step, commit; chords rounded as traced)")
+                          "block step of the binned schedule with FP16 chords (k_drop_bin + k_slab_commit; "
+                          "chords rounded as traced)")
     roof["nonzeros_per_proton"] = sum_nnz / m
     cpu = None
     cpu_err = None
