@@ -91,9 +91,10 @@ def measured_traffic(workload: str, kernel: str):
     return float(t["hbm_bytes_per_launch"]), os.path.relpath(p, ROOT)
 
 
-def measured_fbp_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of an FBP kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the sources changed since."""
+def measured_fbp_traffic(workload: str, kernels):
+    """HBM bytes per launch of FBP kernels (one name, or the kernels of a step
+    summed) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or
+    None when the sources changed since."""
     p = os.path.join(ROOT, "profiles", "traffic_fbp_cyl200.json")
     if not os.path.exists(p):
         return None, "no counter summary"
@@ -102,10 +103,13 @@ def measured_fbp_traffic(workload: str, kernel: str):
         return None, "counters taken on another workload"
     if t.get("sources_sha256") != kernel_sources_digest("fbp"):
         return None, "kernel sources changed since the counters were taken"
-    k = t.get("kernels", {}).get(kernel)
-    if k is None:
-        return None, f"no counters for {kernel}"
-    return float(k["hbm_bytes_per_launch"]), p
+    total = 0.0
+    for kernel in ([kernels] if isinstance(kernels, str) else kernels):
+        k = t.get("kernels", {}).get(kernel)
+        if k is None:
+            return None, f"no counters for {kernel}"
+        total += float(k["hbm_bytes_per_launch"])
+    return total, os.path.relpath(p, ROOT)
 
 
 def count_nonzeros(api, plan, pr, chunk=1 << 20):
@@ -574,14 +578,14 @@ def run_fbp(args):
     stages = {"sinogram_ms": t_sino, "filter_ms": t_filt, "backproject_ms": t_bp}
     if t_bp >= t_sino:
         roof = {"bound": "alu", "achieved": bp_flops / (t_bp * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                "kernel": "k_fbp_backproject (FP64 vector ALU)", "kernel_avg_us": 1e3 * t_bp,
+                "kernel": "k_fbp_backproject_tiled (FP64 vector ALU)", "kernel_avg_us": 1e3 * t_bp,
                 "algorithmic_flops_per_launch": bp_flops}
     else:
         roof = {"bound": "hbm", "achieved": bin_bytes / (t_sino * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
-                "kernel": "k_fbp_clear + k_fbp_bin + k_fbp_mean", "kernel_avg_us": 1e3 * t_sino,
+                "kernel": "k_fbp_clear + k_fbp_bin_lds + k_fbp_mean (the binning step)", "kernel_avg_us": 1e3 * t_sino,
                 "algorithmic_bytes_per_launch": bin_bytes}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    kname = "k_fbp_backproject" if roof["bound"] == "alu" else "k_fbp_bin_lds"
+    kname = "k_fbp_backproject_tiled" if roof["bound"] == "alu" else ["k_fbp_clear", "k_fbp_bin_lds", "k_fbp_mean"]
     traffic, source = measured_fbp_traffic(cfg.name, kname)
     roof["traffic"] = traffic
     roof["traffic_source"] = source

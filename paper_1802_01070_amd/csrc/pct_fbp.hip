@@ -17,7 +17,10 @@
 //                      filtered row, linearly interpolated at the voxel's
 //                      lateral coordinate; the angles' sines and cosines in LDS;
 //                      workgroups of a slice stay on one XCD so that the slice's
-//                      filtered rows are read through one L2
+//                      filtered rows are read through one L2; k_fbp_backproject_tiled,
+//                      the same over 16 x 16 voxel tiles with each angle's
+//                      row window staged in LDS (the default; the untiled
+//                      kernel serves lateral bins much finer than the voxels)
 //
 // Sinograms are laid out [iz][angle][k] (a slice's rows are contiguous).
 
@@ -217,6 +220,100 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject(const double *__rest
     x[int64_t(iz) * plane + v] = T(acc * (M_PI / f.n_ang));
 }
 
+// The same sum over 16 x 16 voxel tiles, angles taken in chunks: for each angle
+// of a chunk the workgroup stages in LDS the window of the filtered row that
+// the tile's lateral coordinates reach (zeros where the window runs past the
+// row), so that the per-sample work has no bounds test and reads LDS only.
+// The lowest bin of angle a's window is one below floor(s) at the tile's
+// lowest corner; its W bins cover the tile's whole lateral span (host bound)
+// and the interpolation neighbour.  Same operations, same angle order and
+// same zero rule as k_fbp_backproject.
+// Grid: 8 * ceil(nz / 8) * tiles workgroups, slices placed on XCDs as there.
+constexpr int kBpTile = 16;
+constexpr int kBpMaxWindow = 512;         // wider windows take k_fbp_backproject
+constexpr int kBpWindowBytes = 24576;     // LDS of one chunk's row windows
+
+template <typename T>
+__global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *__restrict__ q, T *__restrict__ x,
+                                                                  FbpDev f, GridDev g, int tiles_x, int tiles,
+                                                                  int W, int chunk)
+{
+    extern __shared__ double lds[];
+    double *win = lds;                    // chunk * W bins
+    double *cs = lds + int64_t(chunk) * W;
+    double *sn = cs + chunk;
+    int *kb = reinterpret_cast<int *>(sn + chunk);
+    const int L = blockIdx.x;
+    const int xcd = L % 8, j = L / 8;
+    const int iz = xcd + 8 * (j / tiles);
+    const int tile = j % tiles;
+    if (iz >= g.n[2]) return;   // whole workgroup: no barrier below is skipped by part of it
+    const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
+    const int ux = tx0 + int(threadIdx.x) % kBpTile, uy = ty0 + int(threadIdx.x) / kBpTile;
+    const bool mine = ux < g.n[0] && uy < g.n[1];
+    // lanes past the grid's edge compute for the last voxel inside (never stored)
+    const int ix = min(ux, g.n[0] - 1), iy = min(uy, g.n[1] - 1);
+    const double xc = g.lo[0] + (ix + 0.5) * g.pitch[0];
+    const double yc = g.lo[1] + (iy + 0.5) * g.pitch[1];
+    // the tile's corner voxel centres bound every lane's lateral coordinate
+    const double x0c = g.lo[0] + (tx0 + 0.5) * g.pitch[0];
+    const double x1c = g.lo[0] + (min(tx0 + kBpTile, g.n[0]) - 0.5) * g.pitch[0];
+    const double y0c = g.lo[1] + (ty0 + 0.5) * g.pitch[1];
+    const double y1c = g.lo[1] + (min(ty0 + kBpTile, g.n[1]) - 0.5) * g.pitch[1];
+    const double inv_dt = 1.0 / f.dt;
+    const double *qs = q + int64_t(iz) * f.n_ang * f.n_t;
+    double acc = 0.0;
+    for (int a0 = 0; a0 < f.n_ang; a0 += chunk) {
+        const int na = min(chunk, f.n_ang - a0);
+        __syncthreads();   // the previous chunk's windows are no longer read
+        for (int c = threadIdx.x; c < na; c += blockDim.x) {
+            double sa, ca;
+            sincos(double(a0 + c) * f.dphi, &sa, &ca);
+            sn[c] = sa;
+            cs[c] = ca;
+            const double t_lo = fmin(fmin(-x0c * sa + y0c * ca, -x1c * sa + y0c * ca),
+                                     fmin(-x0c * sa + y1c * ca, -x1c * sa + y1c * ca));
+            kb[c] = int(floor((t_lo - f.t0) * inv_dt - 0.5)) - 1;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < na * W; e += blockDim.x) {
+            const int c = e / W;
+            const int k = kb[c] + (e - c * W);
+            win[e] = (k >= 0 && k < f.n_t) ? qs[int64_t(a0 + c) * f.n_t + k] : 0.0;
+        }
+        __syncthreads();
+        for (int c = 0; c < na; ++c) {
+            const double t = -xc * sn[c] + yc * cs[c];
+            const double s = (t - f.t0) * inv_dt - 0.5;
+            const double fk = floor(s);
+            const double w = s - fk;
+            // in [0, W - 2] by the window's construction; the clamp only keeps
+            // the LDS reads inside the chunk
+            const int i = min(max(int(fk) - kb[c], 0), W - 2);
+            const double *row = win + c * W + i;
+            acc += (1.0 - w) * row[0] + w * row[1];
+        }
+    }
+    if (mine) x[int64_t(iz) * g.n[0] * g.n[1] + int64_t(iy) * g.n[0] + ix] = T(acc * (M_PI / f.n_ang));
+}
+
+// Window width (bins) of a tile: its lateral span at any angle is at most
+// (kBpTile - 1) (px + py) (|sin| <= 1, |cos| <= 1); the lowest bin sits one
+// below the lowest corner's and the interpolation reads one past the
+// highest, with a bin of margin for rounding.
+// Geometries whose bin indices at the voxels could leave the int range (a
+// far-off t0) take the untiled kernel too.
+static int fbp_tile_window(const FbpDev &f, const GridDev &g)
+{
+    const double span = (kBpTile - 1) * (g.pitch[0] + g.pitch[1]) / f.dt;
+    if (!(span < double(kBpMaxWindow))) return kBpMaxWindow + 1;
+    const double r = std::hypot(std::max(std::fabs(g.lo[0]), std::fabs(g.hi[0])),
+                                std::max(std::fabs(g.lo[1]), std::fabs(g.hi[1])));
+    const double s_max = (r + std::fabs(f.t0)) / f.dt + 2.0;
+    if (!(s_max < 1073741824.0)) return kBpMaxWindow + 1;
+    return int(std::ceil(span)) + 5;
+}
+
 static unsigned grid_stride_blocks(int64_t n)
 {
     return unsigned(std::max<int64_t>(1, std::min<int64_t>(8192, (n + kFbpWG - 1) / kFbpWG)));
@@ -265,6 +362,22 @@ int launch_fbp_backproject(const FbpDev &f, const GridDev &g, const double *q, v
                            void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int W = fbp_tile_window(f, g);
+    if (W <= kBpMaxWindow) {
+        const int tiles_x = (g.n[0] + kBpTile - 1) / kBpTile;
+        const int tiles = tiles_x * ((g.n[1] + kBpTile - 1) / kBpTile);
+        const int per_angle = W * int(sizeof(double)) + 2 * int(sizeof(double)) + int(sizeof(int));
+        const int chunk = std::max(1, std::min(f.n_ang, kBpWindowBytes / per_angle));
+        const unsigned grid = unsigned(8 * ((g.n[2] + 7) / 8) * int64_t(tiles));
+        const size_t lds = size_t(chunk) * per_angle;
+        if (dtype == PCT_F64)
+            hipLaunchKernelGGL(k_fbp_backproject_tiled<double>, dim3(grid), dim3(kFbpWG), lds, s, q,
+                               static_cast<double *>(x), f, g, tiles_x, tiles, W, chunk);
+        else
+            hipLaunchKernelGGL(k_fbp_backproject_tiled<float>, dim3(grid), dim3(kFbpWG), lds, s, q,
+                               static_cast<float *>(x), f, g, tiles_x, tiles, W, chunk);
+        return hipGetLastError();
+    }
     const int64_t plane = int64_t(g.n[0]) * g.n[1];
     const int tiles = int((plane + kFbpWG - 1) / kFbpWG);
     const unsigned grid = unsigned(8 * ((g.n[2] + 7) / 8) * int64_t(tiles));

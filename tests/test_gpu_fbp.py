@@ -200,3 +200,37 @@ def test_fbp_ignores_the_hull_and_follows_region_grids():
     xr = api.pct_fbp(reg, pr, b, g, dtype=torch.float64).cpu().numpy()
     rx = ofbp.fbp(reg.grid, sc.mlp, sc.protons, sc.b, g.n_angles, g.n_t, g.t0, g.dt)
     assert np.abs(xr - rx).max() <= image_tol(g, rx)
+
+
+# (grid, geometry): the tiled kernel with partial tiles, angles in several
+# chunks, windows that run past either end of the rows, coarse bins and an
+# off-centre grid; the untiled kernel for lateral bins much finer than the
+# voxels and for a far-off t0
+_RAGGED = synth.Grid(37, 23, 11, pitch=(1.5, 2.0, 1.0))
+_OFFSET = synth.Grid(40, 40, 3, origin=(30.0, -70.0, -1.5))
+
+
+@pytest.mark.parametrize("grid,geo", [
+    (_RAGGED, api.FbpGeom.for_grid(_RAGGED, 64, dt=0.75)),
+    (_RAGGED, api.FbpGeom(64, 40, -10.0, 0.75)),
+    (_RAGGED, api.FbpGeom(7, 5, -30.0, 7.0)),
+    (_OFFSET, api.FbpGeom(32, 300, -150.0, 1.0)),
+    (_RAGGED, api.FbpGeom.for_grid(_RAGGED, 24, dt=0.05)),
+    (_RAGGED, api.FbpGeom(16, 8, 1.0e12, 1.0)),
+])
+def test_backprojection_of_random_rows(grid, geo):
+    rng = np.random.default_rng(geo.n_t)
+    rq = rng.standard_normal((grid.nz, geo.n_angles, geo.n_t))
+    say(f"back-projection: grid {grid.nx}x{grid.ny}x{grid.nz}, {geo}")
+    plan = api.Plan(grid, synth.MLPModel(u_in=-60.0, u_out=60.0), DEV)
+    q = torch.from_numpy(rq).to(DEV)
+    x64 = api.pct_fbp_backproject(plan, q, geo, dtype=torch.float64).cpu().numpy()
+    x32 = api.pct_fbp_backproject(plan, q, geo, dtype=torch.float32).cpu().numpy()
+    rx = ofbp.backproject(grid, rq, geo.n_angles, geo.t0, geo.dt)
+    s = max(1.0, np.abs(rx).max())
+    assert np.abs(x64 - rx).max() <= 1e-12 * s
+    assert np.abs(x32 - rx).max() <= 1e-6 * s
+    if geo.t0 > 1e9:
+        assert not rx.any() and not x64.any()
+    else:
+        assert np.count_nonzero(rx) > grid.nvox // 4
