@@ -220,18 +220,22 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject(const double *__rest
     x[int64_t(iz) * plane + v] = T(acc * (M_PI / f.n_ang));
 }
 
-// The same sum over 16 x 16 voxel tiles, angles taken in chunks: for each angle
-// of a chunk the workgroup stages in LDS the window of the filtered row that
-// the tile's lateral coordinates reach (zeros where the window runs past the
-// row), so that the per-sample work has no bounds test and reads LDS only.
-// The lowest bin of angle a's window is one below floor(s) at the tile's
-// lowest corner; its W bins cover the tile's whole lateral span (host bound)
-// and the interpolation neighbour.  Same operations, same angle order and
+// The same sum over 16 x 16 voxel tiles of kBpSlices slices, angles taken in
+// chunks: for each angle of a chunk the workgroup stages in LDS the window of
+// each slice's filtered row that the tile's lateral coordinates reach (zeros
+// where the window runs past the row), so that the per-sample work has no
+// bounds test and reads LDS only, and a thread's voxels at one (x, y) share
+// the lateral coordinate, its bin and weight over the slices.  The lowest bin
+// of angle a's window is one below floor(s) at the tile's lowest corner; its
+// W bins cover the tile's whole lateral span (host bound) and the
+// interpolation neighbour.  Same operations per voxel, same angle order and
 // same zero rule as k_fbp_backproject.
-// Grid: 8 * ceil(nz / 8) * tiles workgroups, slices placed on XCDs as there.
+// Grid: 8 * ceil(ngroups / 8) * tiles workgroups over ngroups = ceil(nz /
+// kBpSlices) slice groups, placed on XCDs as there (group for slice).
 constexpr int kBpTile = 16;
+constexpr int kBpSlices = 4;
 constexpr int kBpMaxWindow = 512;         // wider windows take k_fbp_backproject
-constexpr int kBpWindowBytes = 24576;     // LDS of one chunk's row windows
+constexpr int kBpWindowBytes = 32768;     // LDS of one chunk's row windows
 
 template <typename T>
 __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *__restrict__ q, T *__restrict__ x,
@@ -239,15 +243,15 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *
                                                                   int W, int chunk)
 {
     extern __shared__ double lds[];
-    double *win = lds;                    // chunk * W bins
-    double *cs = lds + int64_t(chunk) * W;
+    double *win = lds;                    // chunk * kBpSlices * W bins
+    double *cs = lds + int64_t(chunk) * kBpSlices * W;
     double *sn = cs + chunk;
     int *kb = reinterpret_cast<int *>(sn + chunk);
     const int L = blockIdx.x;
     const int xcd = L % 8, j = L / 8;
-    const int iz = xcd + 8 * (j / tiles);
+    const int iz0 = kBpSlices * (xcd + 8 * (j / tiles));
     const int tile = j % tiles;
-    if (iz >= g.n[2]) return;   // whole workgroup: no barrier below is skipped by part of it
+    if (iz0 >= g.n[2]) return;   // whole workgroup: no barrier below is skipped by part of it
     const int tx0 = (tile % tiles_x) * kBpTile, ty0 = (tile / tiles_x) * kBpTile;
     const int ux = tx0 + int(threadIdx.x) % kBpTile, uy = ty0 + int(threadIdx.x) / kBpTile;
     const bool mine = ux < g.n[0] && uy < g.n[1];
@@ -261,8 +265,9 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *
     const double y0c = g.lo[1] + (ty0 + 0.5) * g.pitch[1];
     const double y1c = g.lo[1] + (min(ty0 + kBpTile, g.n[1]) - 0.5) * g.pitch[1];
     const double inv_dt = 1.0 / f.dt;
-    const double *qs = q + int64_t(iz) * f.n_ang * f.n_t;
-    double acc = 0.0;
+    const int span = kBpSlices * W;
+    double acc[kBpSlices];
+    for (int z = 0; z < kBpSlices; ++z) acc[z] = 0.0;
     for (int a0 = 0; a0 < f.n_ang; a0 += chunk) {
         const int na = min(chunk, f.n_ang - a0);
         __syncthreads();   // the previous chunk's windows are no longer read
@@ -276,10 +281,14 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *
             kb[c] = int(floor((t_lo - f.t0) * inv_dt - 0.5)) - 1;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < na * W; e += blockDim.x) {
-            const int c = e / W;
-            const int k = kb[c] + (e - c * W);
-            win[e] = (k >= 0 && k < f.n_t) ? qs[int64_t(a0 + c) * f.n_t + k] : 0.0;
+        for (int e = threadIdx.x; e < na * span; e += blockDim.x) {
+            const int c = e / span;
+            const int r = e - c * span;
+            const int z = r / W;
+            const int k = kb[c] + (r - z * W);
+            // slices past the grid's end stage the last slice's rows (never stored)
+            const int iz = min(iz0 + z, g.n[2] - 1);
+            win[e] = (k >= 0 && k < f.n_t) ? q[(int64_t(iz) * f.n_ang + a0 + c) * f.n_t + k] : 0.0;
         }
         __syncthreads();
         for (int c = 0; c < na; ++c) {
@@ -290,11 +299,17 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *
             // in [0, W - 2] by the window's construction; the clamp only keeps
             // the LDS reads inside the chunk
             const int i = min(max(int(fk) - kb[c], 0), W - 2);
-            const double *row = win + c * W + i;
-            acc += (1.0 - w) * row[0] + w * row[1];
+            const double *row = win + c * span + i;
+#pragma unroll
+            for (int z = 0; z < kBpSlices; ++z) acc[z] += (1.0 - w) * row[z * W] + w * row[z * W + 1];
         }
     }
-    if (mine) x[int64_t(iz) * g.n[0] * g.n[1] + int64_t(iy) * g.n[0] + ix] = T(acc * (M_PI / f.n_ang));
+    if (!mine) return;
+    const int64_t plane = int64_t(g.n[0]) * g.n[1];
+    const int64_t v = int64_t(iy) * g.n[0] + ix;
+#pragma unroll
+    for (int z = 0; z < kBpSlices; ++z)
+        if (iz0 + z < g.n[2]) x[int64_t(iz0 + z) * plane + v] = T(acc[z] * (M_PI / f.n_ang));
 }
 
 // Window width (bins) of a tile: its lateral span at any angle is at most
@@ -366,9 +381,10 @@ int launch_fbp_backproject(const FbpDev &f, const GridDev &g, const double *q, v
     if (W <= kBpMaxWindow) {
         const int tiles_x = (g.n[0] + kBpTile - 1) / kBpTile;
         const int tiles = tiles_x * ((g.n[1] + kBpTile - 1) / kBpTile);
-        const int per_angle = W * int(sizeof(double)) + 2 * int(sizeof(double)) + int(sizeof(int));
+        const int per_angle = kBpSlices * W * int(sizeof(double)) + 2 * int(sizeof(double)) + int(sizeof(int));
         const int chunk = std::max(1, std::min(f.n_ang, kBpWindowBytes / per_angle));
-        const unsigned grid = unsigned(8 * ((g.n[2] + 7) / 8) * int64_t(tiles));
+        const int groups = (g.n[2] + kBpSlices - 1) / kBpSlices;
+        const unsigned grid = unsigned(8 * ((groups + 7) / 8) * int64_t(tiles));
         const size_t lds = size_t(chunk) * per_angle;
         if (dtype == PCT_F64)
             hipLaunchKernelGGL(k_fbp_backproject_tiled<double>, dim3(grid), dim3(kFbpWG), lds, s, q,
