@@ -220,22 +220,27 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject(const double *__rest
     x[int64_t(iz) * plane + v] = T(acc * (M_PI / f.n_ang));
 }
 
-// The same sum over 16 x 16 voxel tiles of kBpSlices slices, angles taken in
-// chunks: for each angle of a chunk the workgroup stages in LDS the window of
-// each slice's filtered row that the tile's lateral coordinates reach (zeros
-// where the window runs past the row), so that the per-sample work has no
-// bounds test and reads LDS only, and a thread's voxels at one (x, y) share
-// the lateral coordinate, its bin and weight over the slices.  The lowest bin
-// of angle a's window is one below floor(s) at the tile's lowest corner; its
-// W bins cover the tile's whole lateral span (host bound) and the
+// The same sum over 16 x 16 voxel tiles of kBpSlices slices.  Each angle's
+// sine, cosine and window start are computed once per workgroup; then, chunk
+// by chunk of angles, the workgroup stages in LDS the window of each slice's
+// filtered row that the tile's lateral coordinates reach (zeros where the
+// window runs past the row), so that the per-sample work has no bounds test
+// and reads LDS only, and a thread's voxels at one (x, y) share the lateral
+// coordinate, its bin and weight over the slices.  The next chunk's windows
+// are loaded into registers while the current chunk is summed.  The lowest
+// bin of angle a's window is one below floor(s) at the tile's lowest corner;
+// its W bins cover the tile's whole lateral span (host bound) and the
 // interpolation neighbour.  Same operations per voxel, same angle order and
 // same zero rule as k_fbp_backproject.
 // Grid: 8 * ceil(ngroups / 8) * tiles workgroups over ngroups = ceil(nz /
 // kBpSlices) slice groups, placed on XCDs as there (group for slice).
+// LDS: chunk * kBpSlices * W window bins, then n_ang sines, cosines and
+// window starts; chunk * kBpSlices * W <= kBpPrefetch * kFbpWG.
 constexpr int kBpTile = 16;
 constexpr int kBpSlices = 4;
+constexpr int kBpPrefetch = 16;           // window bins a thread holds for the next chunk
 constexpr int kBpMaxWindow = 512;         // wider windows take k_fbp_backproject
-constexpr int kBpWindowBytes = 32768;     // LDS of one chunk's row windows
+constexpr int kBpAngleBytes = 2 * int(sizeof(double)) + int(sizeof(int));
 
 template <typename T>
 __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *__restrict__ q, T *__restrict__ x,
@@ -243,10 +248,11 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *
                                                                   int W, int chunk)
 {
     extern __shared__ double lds[];
-    double *win = lds;                    // chunk * kBpSlices * W bins
-    double *cs = lds + int64_t(chunk) * kBpSlices * W;
-    double *sn = cs + chunk;
-    int *kb = reinterpret_cast<int *>(sn + chunk);
+    const int span = kBpSlices * W;
+    double *win = lds;                    // chunk * span bins
+    double *cs = lds + int64_t(chunk) * span;
+    double *sn = cs + f.n_ang;
+    int *kb = reinterpret_cast<int *>(sn + f.n_ang);
     const int L = blockIdx.x;
     const int xcd = L % 8, j = L / 8;
     const int iz0 = kBpSlices * (xcd + 8 * (j / tiles));
@@ -265,40 +271,59 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_backproject_tiled(const double *
     const double y0c = g.lo[1] + (ty0 + 0.5) * g.pitch[1];
     const double y1c = g.lo[1] + (min(ty0 + kBpTile, g.n[1]) - 0.5) * g.pitch[1];
     const double inv_dt = 1.0 / f.dt;
-    const int span = kBpSlices * W;
+    for (int a = threadIdx.x; a < f.n_ang; a += blockDim.x) {
+        double sa, ca;
+        sincos(double(a) * f.dphi, &sa, &ca);
+        sn[a] = sa;
+        cs[a] = ca;
+        const double t_lo = fmin(fmin(-x0c * sa + y0c * ca, -x1c * sa + y0c * ca),
+                                 fmin(-x0c * sa + y1c * ca, -x1c * sa + y1c * ca));
+        kb[a] = int(floor((t_lo - f.t0) * inv_dt - 0.5)) - 1;
+    }
+    __syncthreads();
+    // the window bins of angles [a0, a0 + chunk) this thread stages: element e
+    // = threadIdx.x + u * kFbpWG of the chunk's (angle, slice, bin) order
+    double pre[kBpPrefetch];
+    auto fetch = [&](int a0) {
+        const int n = min(chunk, f.n_ang - a0) * span;
+#pragma unroll
+        for (int u = 0; u < kBpPrefetch; ++u) {
+            const int e = int(threadIdx.x) + u * kFbpWG;
+            double v = 0.0;
+            if (e < n) {
+                const int c = e / span;
+                const int r = e - c * span;
+                const int z = r / W;
+                const int k = kb[a0 + c] + (r - z * W);
+                // slices past the grid's end stage the last slice's rows (never stored)
+                const int iz = min(iz0 + z, g.n[2] - 1);
+                if (k >= 0 && k < f.n_t) v = q[(int64_t(iz) * f.n_ang + a0 + c) * f.n_t + k];
+            }
+            pre[u] = v;
+        }
+    };
     double acc[kBpSlices];
     for (int z = 0; z < kBpSlices; ++z) acc[z] = 0.0;
+    fetch(0);
     for (int a0 = 0; a0 < f.n_ang; a0 += chunk) {
         const int na = min(chunk, f.n_ang - a0);
         __syncthreads();   // the previous chunk's windows are no longer read
-        for (int c = threadIdx.x; c < na; c += blockDim.x) {
-            double sa, ca;
-            sincos(double(a0 + c) * f.dphi, &sa, &ca);
-            sn[c] = sa;
-            cs[c] = ca;
-            const double t_lo = fmin(fmin(-x0c * sa + y0c * ca, -x1c * sa + y0c * ca),
-                                     fmin(-x0c * sa + y1c * ca, -x1c * sa + y1c * ca));
-            kb[c] = int(floor((t_lo - f.t0) * inv_dt - 0.5)) - 1;
+#pragma unroll
+        for (int u = 0; u < kBpPrefetch; ++u) {
+            const int e = int(threadIdx.x) + u * kFbpWG;
+            if (e < na * span) win[e] = pre[u];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < na * span; e += blockDim.x) {
-            const int c = e / span;
-            const int r = e - c * span;
-            const int z = r / W;
-            const int k = kb[c] + (r - z * W);
-            // slices past the grid's end stage the last slice's rows (never stored)
-            const int iz = min(iz0 + z, g.n[2] - 1);
-            win[e] = (k >= 0 && k < f.n_t) ? q[(int64_t(iz) * f.n_ang + a0 + c) * f.n_t + k] : 0.0;
-        }
-        __syncthreads();
+        if (a0 + chunk < f.n_ang) fetch(a0 + chunk);
         for (int c = 0; c < na; ++c) {
-            const double t = -xc * sn[c] + yc * cs[c];
+            const int a = a0 + c;
+            const double t = -xc * sn[a] + yc * cs[a];
             const double s = (t - f.t0) * inv_dt - 0.5;
             const double fk = floor(s);
             const double w = s - fk;
             // in [0, W - 2] by the window's construction; the clamp only keeps
             // the LDS reads inside the chunk
-            const int i = min(max(int(fk) - kb[c], 0), W - 2);
+            const int i = min(max(int(fk) - kb[a], 0), W - 2);
             const double *row = win + c * span + i;
 #pragma unroll
             for (int z = 0; z < kBpSlices; ++z) acc[z] += (1.0 - w) * row[z * W] + w * row[z * W + 1];
@@ -327,6 +352,19 @@ static int fbp_tile_window(const FbpDev &f, const GridDev &g)
     const double s_max = (r + std::fabs(f.t0)) / f.dt + 2.0;
     if (!(s_max < 1073741824.0)) return kBpMaxWindow + 1;
     return int(std::ceil(span)) + 5;
+}
+
+// Angles per chunk of the tiled kernel: the windows and every angle's sine,
+// cosine and window start fit 32 KB of LDS (64 KB when the angles alone take
+// more than 8 KB), and a thread holds at most kBpPrefetch of the next chunk's
+// bins; 0 when not even one angle fits (k_fbp_backproject then).
+static int fbp_tile_chunk(const FbpDev &f, int W)
+{
+    const int span_bytes = kBpSlices * W * int(sizeof(double));
+    const int meta = f.n_ang * kBpAngleBytes;
+    const int budget = meta <= 8192 ? 32768 : 65536;
+    if (meta >= budget) return 0;
+    return std::min({f.n_ang, (budget - meta) / span_bytes, kBpPrefetch * kFbpWG / (kBpSlices * W)});
 }
 
 static unsigned grid_stride_blocks(int64_t n)
@@ -378,14 +416,13 @@ int launch_fbp_backproject(const FbpDev &f, const GridDev &g, const double *q, v
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int W = fbp_tile_window(f, g);
-    if (W <= kBpMaxWindow) {
+    if (W <= kBpMaxWindow && fbp_tile_chunk(f, W) > 0) {
         const int tiles_x = (g.n[0] + kBpTile - 1) / kBpTile;
         const int tiles = tiles_x * ((g.n[1] + kBpTile - 1) / kBpTile);
-        const int per_angle = kBpSlices * W * int(sizeof(double)) + 2 * int(sizeof(double)) + int(sizeof(int));
-        const int chunk = std::max(1, std::min(f.n_ang, kBpWindowBytes / per_angle));
+        const int chunk = fbp_tile_chunk(f, W);
         const int groups = (g.n[2] + kBpSlices - 1) / kBpSlices;
         const unsigned grid = unsigned(8 * ((groups + 7) / 8) * int64_t(tiles));
-        const size_t lds = size_t(chunk) * per_angle;
+        const size_t lds = size_t(chunk) * kBpSlices * W * sizeof(double) + size_t(f.n_ang) * kBpAngleBytes;
         if (dtype == PCT_F64)
             hipLaunchKernelGGL(k_fbp_backproject_tiled<double>, dim3(grid), dim3(kFbpWG), lds, s, q,
                                static_cast<double *>(x), f, g, tiles_x, tiles, W, chunk);

@@ -203,9 +203,10 @@ def test_fbp_ignores_the_hull_and_follows_region_grids():
 
 
 # (grid, geometry): the tiled kernel with partial tiles, angles in several
-# chunks, windows that run past either end of the rows, coarse bins and an
-# off-centre grid; the untiled kernel for lateral bins much finer than the
-# voxels and for a far-off t0
+# chunks, windows that run past either end of the rows, coarse bins, an
+# off-centre grid, and angle sets whose sines, cosines and window starts take
+# more than 8 KB of LDS; the untiled kernel for lateral bins much finer than
+# the voxels, for a far-off t0 and for 4096 angles
 _RAGGED = synth.Grid(37, 23, 11, pitch=(1.5, 2.0, 1.0))
 _OFFSET = synth.Grid(40, 40, 3, origin=(30.0, -70.0, -1.5))
 
@@ -215,6 +216,9 @@ _OFFSET = synth.Grid(40, 40, 3, origin=(30.0, -70.0, -1.5))
     (_RAGGED, api.FbpGeom(64, 40, -10.0, 0.75)),
     (_RAGGED, api.FbpGeom(7, 5, -30.0, 7.0)),
     (_OFFSET, api.FbpGeom(32, 300, -150.0, 1.0)),
+    (_RAGGED, api.FbpGeom.for_grid(_RAGGED, 400, dt=0.75)),
+    (_RAGGED, api.FbpGeom.for_grid(_RAGGED, 600, dt=0.75)),
+    (_RAGGED, api.FbpGeom.for_grid(_RAGGED, 4096, dt=0.75)),
     (_RAGGED, api.FbpGeom.for_grid(_RAGGED, 24, dt=0.05)),
     (_RAGGED, api.FbpGeom(16, 8, 1.0e12, 1.0)),
 ])
