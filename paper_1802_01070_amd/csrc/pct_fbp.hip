@@ -11,8 +11,10 @@
 //                      not fit (integer sums: the result does not depend on the
 //                      order or on the kernel)
 //   k_fbp_mean         one thread per bin: projection = mean WEPL (0 if empty)
-//   k_fbp_filter       one workgroup per (slice, angle) row: Ram-Lak ramp
-//                      filter as a direct convolution over the row, staged in LDS
+//   k_fbp_filter       Ram-Lak ramp filter as a direct convolution over each
+//                      (slice, angle) row: rows staged in LDS, a thread sums
+//                      eight outputs of one parity over blocks of eight taps
+//                      from row values held in registers
 //   k_fbp_backproject  one thread per voxel: sum over the angles of the
 //                      filtered row, linearly interpolated at the voxel's
 //                      lateral coordinate; the angles' sines and cosines in LDS;
@@ -150,32 +152,64 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_mean(const unsigned long long *_
 }
 
 // q_k = dt sum_n p_n h(k - n) with h(0) = 1/(4 dt^2), h(m) = -1/(pi^2 m^2 dt^2)
-// for odd m, 0 for even m: q_k = (p_k / 4 - sum_{odd m} p_{k-m} / (pi^2 m^2)) / dt.
-// LDS: the row (n_t doubles) and the odd-tap coefficients 1/(pi^2 m^2) (n_t).
+// for odd m, 0 for even m: q_k = (p_k / 4 - sum_{odd m} p_{k-m} / (pi^2 m^2)) / dt,
+// p zero outside the row.  A workgroup takes rpw rows (staged in LDS with the
+// odd-tap coefficients c_p = 1/(pi^2 (2p+1)^2), padded with zero taps to a
+// multiple of kFilterR); a thread computes kFilterR outputs of one parity,
+// k0 + 2j, over blocks of kFilterR taps: the 2 kFilterR - 1 row values each
+// side that a block needs are read once into registers, so the LDS reads per
+// (output, tap) drop from two to about 4 / kFilterR.  Each output still sums
+// its taps in ascending m, as the definition is written.
+constexpr int kFilterR = 8;
+
 __global__ void __launch_bounds__(kFbpWG) k_fbp_filter(const double *__restrict__ proj, double *__restrict__ q,
-                                                       int n_t, double dt)
+                                                       int64_t rows, int n_t, double dt, int rpw, int gpr)
 {
     extern __shared__ double lds[];
-    double *row = lds;
-    double *cm = lds + n_t;
-    const int64_t base = int64_t(blockIdx.x) * n_t;
-    for (int k = threadIdx.x; k < n_t; k += blockDim.x) {
-        row[k] = proj[base + k];
-        const double m = double(k);
-        cm[k] = (k & 1) ? 1.0 / (M_PI * M_PI * m * m) : 0.0;
+    const int ntaps = n_t / 2;                                            // odd m = 2p + 1 < n_t
+    const int ptaps = (ntaps + kFilterR - 1) / kFilterR * kFilterR;
+    double *cm = lds;                  // ptaps coefficients, zero past ntaps
+    double *rl = lds + ptaps;          // rpw rows of n_t
+    const int64_t r0 = int64_t(blockIdx.x) * rpw;
+    const int nr = int(min(int64_t(rpw), rows - r0));
+    for (int p = threadIdx.x; p < ptaps; p += blockDim.x) {
+        const double m = double(2 * p + 1);
+        cm[p] = p < ntaps ? 1.0 / (M_PI * M_PI * m * m) : 0.0;
     }
+    for (int i = threadIdx.x; i < nr * n_t; i += blockDim.x) rl[i] = proj[r0 * n_t + i];
     __syncthreads();
     const double inv_dt = 1.0 / dt;
-    for (int k = threadIdx.x; k < n_t; k += blockDim.x) {
-        double acc = 0.0;
-        // odd distances m = 1, 3, ... on both sides of k
-        for (int m = 1; m < n_t; m += 2) {
-            const double c = cm[m];
-            const double lo = k - m >= 0 ? row[k - m] : 0.0;
-            const double hi = k + m < n_t ? row[k + m] : 0.0;
-            acc += c * (lo + hi);
+    for (int wi = threadIdx.x; wi < nr * gpr; wi += blockDim.x) {
+        const int r = wi / gpr, gi = wi - r * gpr;
+        const int k0 = (gi & 1) + 2 * kFilterR * (gi >> 1);
+        const double *row = rl + r * n_t;
+        double acc[kFilterR];
+#pragma unroll
+        for (int j = 0; j < kFilterR; ++j) acc[j] = 0.0;
+        for (int p0 = 0; p0 < ptaps; p0 += kFilterR) {
+            // lo[d]: p_{k0 - 1 - 2 p0 + 2 (d - R + 1)}, the k - m term of output j and
+            // tap p0 + pp at d = j - pp + R - 1; hi[d]: p_{k0 + 1 + 2 p0 + 2 d}, the k + m
+            // term at d = j + pp
+            double lo[2 * kFilterR - 1], hi[2 * kFilterR - 1];
+#pragma unroll
+            for (int d = 0; d < 2 * kFilterR - 1; ++d) {
+                const int il = k0 - 1 - 2 * p0 + 2 * (d - (kFilterR - 1));
+                const int ih = k0 + 1 + 2 * p0 + 2 * d;
+                lo[d] = il >= 0 && il < n_t ? row[il] : 0.0;
+                hi[d] = ih < n_t ? row[ih] : 0.0;
+            }
+#pragma unroll
+            for (int pp = 0; pp < kFilterR; ++pp) {
+                const double c = cm[p0 + pp];
+#pragma unroll
+                for (int j = 0; j < kFilterR; ++j) acc[j] += c * (lo[j - pp + kFilterR - 1] + hi[j + pp]);
+            }
         }
-        q[base + k] = (0.25 * row[k] - acc) * inv_dt;
+#pragma unroll
+        for (int j = 0; j < kFilterR; ++j) {
+            const int k = k0 + 2 * j;
+            if (k < n_t) q[(r0 + r) * n_t + k] = (0.25 * row[k] - acc[j]) * inv_dt;
+        }
     }
 }
 
@@ -405,9 +439,15 @@ int launch_fbp_sinogram(const FbpDev &f, const ProtonsDev &p, int64_t n, const f
 int launch_fbp_filter(const FbpDev &f, const double *proj, double *q, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const unsigned rows = unsigned(int64_t(f.nz) * f.n_ang);
-    hipLaunchKernelGGL(k_fbp_filter, dim3(rows), dim3(kFbpWG), size_t(2) * f.n_t * sizeof(double), s, proj, q,
-                       f.n_t, f.dt);
+    const int64_t rows = int64_t(f.nz) * f.n_ang;
+    // work items of a row: kFilterR-output groups of each parity; rows per
+    // workgroup so that about kFbpWG items share it
+    const int gpr = 2 * (((f.n_t + 1) / 2 + kFilterR - 1) / kFilterR);
+    const int rpw = std::max(1, kFbpWG / gpr);
+    const int ptaps = (f.n_t / 2 + kFilterR - 1) / kFilterR * kFilterR;
+    const size_t lds = (size_t(ptaps) + size_t(rpw) * f.n_t) * sizeof(double);
+    hipLaunchKernelGGL(k_fbp_filter, dim3(unsigned((rows + rpw - 1) / rpw)), dim3(kFbpWG), lds, s, proj, q, rows,
+                       f.n_t, f.dt, rpw, gpr);
     return hipGetLastError();
 }
 

@@ -238,3 +238,16 @@ def test_backprojection_of_random_rows(grid, geo):
         assert not rx.any() and not x64.any()
     else:
         assert np.count_nonzero(rx) > grid.nvox // 4
+
+
+@pytest.mark.parametrize("n_t", [1, 2, 17, 37, 284, 4096])
+def test_filter_of_random_rows(n_t):
+    # rows shorter than one output group, ragged groups of both parities, and
+    # rows long enough that one row fills a workgroup
+    grid = synth.Grid(8, 8, 3)
+    plan = api.Plan(grid, synth.MLPModel(u_in=-20.0, u_out=20.0), DEV)
+    geo = api.FbpGeom(5, n_t, -0.5 * n_t * 0.7, 0.7)
+    rp = np.random.default_rng(n_t).standard_normal((grid.nz, geo.n_angles, n_t))
+    q = api.pct_fbp_filter(plan, torch.from_numpy(rp).to(DEV), geo).cpu().numpy()
+    rq = ofbp.filter_rows(rp, geo.dt)
+    assert np.abs(q - rq).max() <= 1e-12 * max(1.0, np.abs(rq).max())
