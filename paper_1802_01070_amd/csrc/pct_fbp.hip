@@ -83,8 +83,12 @@ __global__ void __launch_bounds__(kFbpWG) k_fbp_bin(ProtonsDev p, const float *_
 // of k_fbp_bin bit for bit.
 constexpr double kFbpLdsWepl = 1024.0;
 constexpr int64_t kFbpMaxChunk = 8192;
+// 1024 threads share the (up to 64 KB and more) LDS histogram: one or two
+// workgroups fill a CU's LDS, so the workgroup is made wide to keep enough
+// waves in flight over the chunk's loads and LDS atomics
+constexpr int kFbpBinWG = 1024;
 
-__global__ void __launch_bounds__(kFbpWG) k_fbp_bin_lds(ProtonsDev p, const float *__restrict__ b, int64_t n,
+__global__ void __launch_bounds__(kFbpBinWG) k_fbp_bin_lds(ProtonsDev p, const float *__restrict__ b, int64_t n,
                                                         int64_t chunk, FbpDev f, unsigned long long *sum,
                                                         unsigned *cnt)
 {
@@ -426,7 +430,7 @@ int launch_fbp_sinogram(const FbpDev &f, const ProtonsDev &p, int64_t n, const f
         (void)hipGetLastError();
         if (priv) {
             const int64_t chunk = std::min<int64_t>(kFbpMaxChunk, std::max<int64_t>(1024, (n + 1023) / 1024));
-            hipLaunchKernelGGL(k_fbp_bin_lds, dim3(unsigned((n + chunk - 1) / chunk)), dim3(kFbpWG), lds, s, p, b, n,
+            hipLaunchKernelGGL(k_fbp_bin_lds, dim3(unsigned((n + chunk - 1) / chunk)), dim3(kFbpBinWG), lds, s, p, b, n,
                                chunk, f, sum, cnt);
         } else {
             hipLaunchKernelGGL(k_fbp_bin, dim3(grid_stride_blocks(n)), dim3(kFbpWG), 0, s, p, b, n, f, sum, cnt);
